@@ -1,0 +1,141 @@
+/*
+ * rp.h -- C ABI of librp: parallel in-place random permutation on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Gu, Obeya, Shun, "Parallel In-Place Algorithms: Theory and
+ * Practice", Section 4.1, the Knuth-Shuffle listing): given an array A of n
+ * records and swap targets H with 0 <= H[i] <= i, apply
+ *
+ *     for i = n-1 down to 0:  swap(A[i], A[H[i]])
+ *
+ * (the paper writes it 1-based, i = n..1 and H[i] in [1, i]).  The library
+ * computes exactly this permutation, bit for bit, with the relaxed-PIP
+ * algorithm of Section 4.1 (rounds over the first k unfinished swaps, k about
+ * n^(1-eps), Theorem on relaxed-PIP random permutation via the Decomposable
+ * Property of Section 4) implemented in the RP-Final form of Section 7.4 and
+ * Appendix A.2 (single reservation on R[H[i]], dense array for the keys of
+ * the swaps added in the current round, hash table for the rest).  Auxiliary
+ * space is O(n^(1-eps)) words: every byte of device memory a call allocates
+ * is counted and the total never exceeds 8 * floor(n^(1-eps)) bytes.
+ *
+ * Conventions
+ *   - A word is 8 bytes.
+ *   - Pointers are device pointers unless a comment says "host".
+ *   - hipStream_t is passed as void* so this header needs no HIP headers;
+ *     NULL means the null (default) stream.
+ *   - Calls are stream-ordered: the permutation is complete when the stream
+ *     reaches the work the call enqueued.  Unless a comment says otherwise a
+ *     call does not wait for the GPU.
+ *   - Every call that returns an error leaves A untouched.
+ *   - n must be below 2^32 (indices are packed into 32-bit slots).
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define RP_OK 0
+#define RP_PENDING 1   /* rp_batch_poll: not finished yet */
+#define RP_EINVAL (-1) /* bad argument, or some H[i] > i */
+#define RP_ENOMEM (-2) /* device memory or the auxiliary budget cannot be met */
+#define RP_EDEVICE (-3) /* a HIP runtime call failed */
+#define RP_ETIMEOUT (-4) /* device watchdog fired (a barrier or the round count
+                            exceeded its bound); reported through stats */
+
+/*
+ * Per-call statistics, written by the device and copied into caller memory
+ * (host) when the stream reaches the end of the call.
+ *   k                 active-swap capacity per round (the prefix size)
+ *   aux_words         device memory the call allocated, in 8-byte words
+ *                     (rounded up); includes tables, bitmaps, barrier flags
+ *                     and counters
+ *   aux_bound_words   floor(n^(1-eps))
+ *   rounds            reserve/commit rounds executed
+ *   attempts          swap attempts summed over rounds (self-loops excluded)
+ *   retries           attempts that lost and were carried to the next round
+ *   max_active        largest number of swaps attempted in one round
+ *   self_loops        swaps with H[i] = i, retired without a reservation
+ *   grid, slots_per_lane, buckets   launch shape and table size used
+ *   status            RP_OK, or RP_ETIMEOUT if the device watchdog fired
+ */
+typedef struct rp_stats {
+    uint64_t k;
+    uint64_t aux_words;
+    uint64_t aux_bound_words;
+    uint64_t rounds;
+    uint64_t attempts;
+    uint64_t retries;
+    uint64_t max_active;
+    uint64_t self_loops;
+    uint64_t grid;
+    uint64_t slots_per_lane;
+    uint64_t buckets;
+    int64_t status;
+} rp_stats;
+
+/*
+ * floor(n^(1-eps)): the auxiliary-space bound in words (Section 3.2, the
+ * relaxed PIP model's O(n^(1-eps)) auxiliary space; Section 4.1's prefix of
+ * n^(1-eps) swaps).  Pure host arithmetic, no GPU.  Returns 0 for n == 0 or
+ * eps outside (0, 1).
+ */
+uint64_t rp_aux_bound_words(uint64_t n, double eps);
+
+/*
+ * Plan a call without running it (host only, no GPU): fills *stats_out
+ * (host) with the k, aux_words, aux_bound_words, grid, slots_per_lane and
+ * buckets that rp_shuffle_inplace would use on device `device` for these
+ * arguments; the other fields are zero.  Returns RP_OK, RP_EINVAL or
+ * RP_ENOMEM (bound too small for even one active swap).  device < 0 assumes
+ * an MI355X with 256 compute units.
+ */
+int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
+            rp_stats *stats_out);
+
+/*
+ * Shuffle A in place (Section 4.1; the RP-Final implementation of
+ * Section 7.4 / Appendix A.2).
+ *   A           n records of elem_bytes bytes each, contiguous (device).
+ *               Permuted in place; the caller owns it.
+ *   n           number of records, n < 2^32.  n <= 1 is a successful no-op.
+ *   elem_bytes  record size: a multiple of 4 in [4, 256].
+ *   H           swap targets, n uint64 values with H[i] <= i (device,
+ *               read-only, not counted as auxiliary space), or NULL for
+ *               seed mode: H[i] = splitmix64(seed ^ i) mod (i + 1), with
+ *               SplitMix64 as published by Steele, Lea and Flood (2014).
+ *   seed        used only in seed mode.
+ *   eps         in (0, 1); auxiliary space is at most floor(n^(1-eps))
+ *               words.
+ *   stream      hipStream_t (as void*), or NULL.
+ *   stats       host memory (pinned, or pageable at the cost of a
+ *               synchronous copy) receiving rp_stats when the stream reaches
+ *               the end of the call; may be NULL.
+ * Errors: RP_EINVAL for A == NULL with n > 1, a bad elem_bytes or eps,
+ * n >= 2^32, or (H mode) some H[i] > i -- H mode validates H on the device
+ * first and, for that check only, waits for the stream before returning.
+ * RP_ENOMEM if device memory for the auxiliary structures cannot be had.
+ * RP_EDEVICE if a HIP call fails.  A is untouched whenever an error is
+ * returned.  A device watchdog error is reported in stats->status.
+ */
+int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
+                       const uint64_t *H, uint64_t seed, double eps,
+                       void *stream, rp_stats *stats);
+
+/*
+ * Seed-mode swap targets on the device, for testing the exact integer path:
+ * out[j] = splitmix64(seed ^ idx[j]) mod (idx[j] + 1) for j < count, with
+ * idx[j] < 2^32.  idx and out are device arrays.  Stream-ordered.
+ */
+int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
+                    uint64_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RP_H */

@@ -79,6 +79,11 @@ def splitmix64(x: int) -> int:
     return int(_load().oracle_splitmix64(x & (2**64 - 1)))
 
 
+def seed_target(seed: int, i: int) -> int:
+    """H[i] = splitmix64(seed ^ i) mod (i + 1) for one index."""
+    return int(_load().oracle_seed_target(seed & (2**64 - 1), i))
+
+
 def seed_targets(n: int, seed: int) -> np.ndarray:
     """H[i] = splitmix64(seed ^ i) mod (i + 1) for i in [0, n), as uint64."""
     H = np.empty(n, dtype=np.uint64)

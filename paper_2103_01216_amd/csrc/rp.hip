@@ -1,0 +1,1008 @@
+// librp: parallel in-place random permutation for MI355X (gfx950).
+//
+// Computes exactly the sequential Knuth shuffle (Gu, Obeya, Shun, "Parallel
+// In-Place Algorithms: Theory and Practice", Section 4.1) with the relaxed-PIP
+// round structure of Section 4.1 (work on the first k unfinished swaps, k on
+// the order of n^(1-eps)), realised as the RP-Final scheme of Section 7.4 and
+// Appendix A.2: one reservation per swap on R[H[s]], a dense array for the
+// keys of the swaps added in the current round, a hash table for all other
+// keys.  See include/rp.h for the ABI.
+//
+// Execution model on the GPU
+// --------------------------
+// One persistent cooperative kernel runs every round.  Each lane owns up to M
+// swap slots held in registers (the active list); a slot is either empty or
+// holds an unfinished swap (s, H[s]).  A round is
+//   1. gather   all workgroups exchange (free slots, active swaps) through a
+//               flag all-gather; from it every workgroup derives the same new
+//               cursor and its own contiguous share of the fresh indices, so
+//               the active set is always the top unfinished swaps in the
+//               sequential order (decreasing index), as the paper requires;
+//   2. refill   free slots take fresh indices (decreasing), H[s] is computed
+//               (seed mode) or read; self-loops retire at once (Section 4.1
+//               removes them; a swap with H[s] = s is a no-op);
+//   3. reserve  each active swap adds itself to the bucket of key H[s] in
+//               the slot table (the priority write: the largest source, i.e.
+//               the earliest swap in sequential order, is the one that
+//               wins), and sets bit H[s] of the dense window if H[s] lies in
+//               this round's fresh range;
+//   4. barrier
+//   5. commit   swap s wins iff no active swap with a larger source targets
+//               H[s] (bucket of H[s]) and no active swap targets s (dense
+//               window bit for fresh sources, bucket of s otherwise); this is
+//               the single-reservation test of Appendix A.2.  Winners swap
+//               A[s] and A[H[s]]; losers stay in their slots for the next
+//               round (the paper's pack step becomes a per-workgroup prefix
+//               sum over free slots in step 1).
+// Tables are double-buffered by round parity and the stale parity is cleared
+// during step 3, which is the cleaning phase of Appendix A.1.
+//
+// Slot table layout (all 32-bit words, device memory):
+//   ent[b * C + j]      j < C: source index of the j-th swap that reserved
+//                       bucket b this round (key implicit: H[source])
+//   cnt[par * nb + b]   number of reservations into bucket b this round
+//   ovf[par * nb + b]   1 + largest source whose reservation found bucket b
+//                       full (0 = none); such a bucket makes every
+//                       lower-priority swap on it lose, which is exact-safe
+//   bm[par * bmw + i]   dense window bits: bit x set iff some active swap
+//                       targets cursor_new + x
+// Cross-workgroup data is accessed only with relaxed agent-scope atomic loads
+// and stores (device-coherent, never a stale cache hit); a workgroup waits
+// for all of its memory operations to complete before it publishes its
+// barrier flag, and every access after a barrier is issued after the flags
+// were observed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "rp.h"
+
+namespace {
+
+constexpr int WG = 256;                 // threads per workgroup
+constexpr int WAVES = WG / 64;
+constexpr int BUCKET = 16;              // entries per bucket (one 64-byte line)
+constexpr int LAMBDA = 8;               // target reservations per bucket
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+constexpr int MAXG = 2048;              // largest grid the gather supports
+constexpr uint64_t WATCHDOG_TICKS = 500000000ull;  // 5 s at 100 MHz
+
+struct Params {
+    unsigned char *A;
+    const uint64_t *H;   // nullptr: seed mode
+    uint64_t seed;
+    uint32_t n;
+    uint32_t eb;
+    uint32_t k;
+    uint32_t nb;
+    uint32_t bmw;
+    uint32_t *ent;
+    uint32_t *cnt;
+    uint32_t *ovf;
+    uint32_t *bm;
+    uint64_t *flags;
+    uint32_t *err;
+    uint64_t *dstats;    // rp_stats laid out as 12 x 64-bit words
+    uint64_t max_rounds;
+};
+
+// rp_stats word indices
+enum { S_K, S_AUX, S_BOUND, S_ROUNDS, S_ATTEMPTS, S_RETRIES, S_MAXACT,
+       S_SELF, S_GRID, S_SLOTS, S_BUCKETS, S_STATUS, S_WORDS };
+
+// ---------------------------------------------------------------- memory ops
+
+template <typename T>
+__device__ __forceinline__ T ld(const T *p)
+{
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wait_mem()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// ------------------------------------------------------- exact integer math
+
+// SplitMix64 output function (Steele, Lea, Flood 2014): add the golden-ratio
+// increment, two xor-shift-multiply rounds, final xor-shift, all mod 2^64.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Exact x mod d for 1 <= d <= 2^32 without an integer divider.  Quotient
+// estimate from an IEEE-754 double reciprocal, then one exact correction in
+// 64-bit integers: the estimate q is within 8193 of x/d (three roundings of
+// relative size 2^-53 on a value below 2^64, a clamp of at most 2048 and a
+// truncation), so r = x - q*d lies in (-2^46, 2^46) and is exact in int64;
+// r/d is then resolved in doubles to within 2^-39, which leaves r within one
+// d of [0, d) -- two conditional corrections each way finish it.
+__device__ __forceinline__ uint64_t umod64(uint64_t x, uint64_t d)
+{
+    const double rd = 1.0 / (double)d;
+    double qf = (double)x * rd;
+    qf = fmin(qf, 18446744073709549568.0);  // largest double below 2^64
+    const uint64_t q = (uint64_t)qf;
+    int64_t r = (int64_t)(x - q * d);
+    const int64_t q2 = (int64_t)((double)r * rd);
+    r -= q2 * (int64_t)d;
+    const int64_t sd = (int64_t)d;
+    if (r < 0) r += sd;
+    if (r < 0) r += sd;
+    if (r >= sd) r -= sd;
+    if (r >= sd) r -= sd;
+    return (uint64_t)r;
+}
+
+// Swap target of iteration i in seed mode, i < 2^32.
+__device__ __forceinline__ uint32_t seed_target(uint64_t seed, uint64_t i)
+{
+    return (uint32_t)umod64(splitmix64(seed ^ i), i + 1);
+}
+
+__device__ __forceinline__ uint32_t target_of(const Params &p, uint32_t s)
+{
+    return p.H ? (uint32_t)p.H[s] : seed_target(p.seed, s);
+}
+
+__device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t nb)
+{
+    const uint32_t h = (uint32_t)(((uint64_t)key * 0x9E3779B97F4A7C15ull) >> 32);
+    return (uint32_t)(((uint64_t)h * nb) >> 32);
+}
+
+// ----------------------------------------------------- workgroup reductions
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o)
+            v += u;
+    }
+    return v;
+}
+
+// Exclusive prefix of v over the workgroup; *total gets the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total,
+                                                    uint32_t *sh)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t incl = wave_incl_scan(v);
+    __syncthreads();
+    if (lane == 63)
+        sh[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int i = 0; i < WAVES; i++) {
+        const uint32_t x = sh[i];
+        base += (i < wave) ? x : 0;
+        tot += x;
+    }
+    *total = tot;
+    return base + incl - v;
+}
+
+// Sum of a, b, c over the workgroup (uniform result).
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void block_sum3(uint64_t &a, uint64_t &b, uint64_t &c,
+                                           uint64_t *sh)
+{
+    a = wave_sum64(a);
+    b = wave_sum64(b);
+    c = wave_sum64(c);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) {
+        sh[3 * wave] = a;
+        sh[3 * wave + 1] = b;
+        sh[3 * wave + 2] = c;
+    }
+    __syncthreads();
+    a = b = c = 0;
+    for (int i = 0; i < WAVES; i++) {
+        a += sh[3 * i];
+        b += sh[3 * i + 1];
+        c += sh[3 * i + 2];
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- the gather
+
+// Publish `payload` under `epoch` and collect every workgroup's payload for
+// the same epoch into sh_pay[0..G).  Doubles as the grid barrier: it returns
+// only after every workgroup published, and this workgroup's memory
+// operations complete before its flag is written.  Flags are double-buffered
+// by epoch parity: a workgroup cannot publish epoch e+2 before every
+// workgroup has read epoch e.  Returns false when the watchdog fired.
+__device__ bool gather(const Params &p, uint32_t epoch, uint32_t payload,
+                       uint32_t *sh_pay, int *sh_bad)
+{
+    const uint32_t G = gridDim.x;
+    wait_mem();
+    if (threadIdx.x == 0)
+        *sh_bad = 0;
+    __syncthreads();
+    if (G == 1) {
+        if (threadIdx.x == 0)
+            sh_pay[0] = payload;
+        __syncthreads();
+        return true;
+    }
+    uint64_t *fl = p.flags + (uint64_t)(epoch & 1u) * G;
+    if (threadIdx.x == 0)
+        st(&fl[blockIdx.x], ((uint64_t)epoch << 32) | payload);
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    bool bad = false;
+    for (uint32_t v = threadIdx.x; v < G && !bad; v += WG) {
+        uint64_t f = ld(&fl[v]);
+        while ((uint32_t)(f >> 32) != epoch) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > WATCHDOG_TICKS ||
+                ld(p.err) != 0u) {
+                st(p.err, 1u);
+                bad = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            f = ld(&fl[v]);
+        }
+        sh_pay[v] = (uint32_t)f;
+    }
+    if (bad)
+        *sh_bad = 1;
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    return *sh_bad == 0;
+}
+
+// ------------------------------------------------------------ record moves
+
+// Records of EB bytes held in registers (EB = 4, 8, 16).
+template <int EB> struct Rec;
+template <> struct Rec<4> {
+    uint32_t w;
+    __device__ void load(const unsigned char *A, uint32_t i)
+    { w = ld(reinterpret_cast<const uint32_t *>(A) + i); }
+    __device__ void store(unsigned char *A, uint32_t i) const
+    { st(reinterpret_cast<uint32_t *>(A) + i, w); }
+};
+template <> struct Rec<8> {
+    uint64_t w;
+    __device__ void load(const unsigned char *A, uint32_t i)
+    { w = ld(reinterpret_cast<const uint64_t *>(A) + i); }
+    __device__ void store(unsigned char *A, uint32_t i) const
+    { st(reinterpret_cast<uint64_t *>(A) + i, w); }
+};
+template <> struct Rec<16> {
+    uint64_t w0, w1;
+    __device__ void load(const unsigned char *A, uint32_t i)
+    {
+        const uint64_t *q = reinterpret_cast<const uint64_t *>(A) + 2ull * i;
+        w0 = ld(q);
+        w1 = ld(q + 1);
+    }
+    __device__ void store(unsigned char *A, uint32_t i) const
+    {
+        uint64_t *q = reinterpret_cast<uint64_t *>(A) + 2ull * i;
+        st(q, w0);
+        st(q + 1, w1);
+    }
+};
+
+// Swap two records of eb bytes (multiple of 4) word by word.
+__device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
+                                             uint32_t a, uint32_t b)
+{
+    if ((eb & 7u) == 0) {
+        uint64_t *pa = reinterpret_cast<uint64_t *>(A + (uint64_t)a * eb);
+        uint64_t *pb = reinterpret_cast<uint64_t *>(A + (uint64_t)b * eb);
+        for (uint32_t j = 0; j < eb / 8; j += 4) {
+            uint64_t x[4], y[4];
+            const uint32_t m = min(4u, eb / 8 - j);
+            for (uint32_t u = 0; u < 4; u++)
+                if (u < m) { x[u] = ld(pa + j + u); y[u] = ld(pb + j + u); }
+            for (uint32_t u = 0; u < 4; u++)
+                if (u < m) { st(pa + j + u, y[u]); st(pb + j + u, x[u]); }
+        }
+    } else {
+        uint32_t *pa = reinterpret_cast<uint32_t *>(A + (uint64_t)a * eb);
+        uint32_t *pb = reinterpret_cast<uint32_t *>(A + (uint64_t)b * eb);
+        for (uint32_t j = 0; j < eb / 4; j++) {
+            const uint32_t x = ld(pa + j), y = ld(pb + j);
+            st(pa + j, y);
+            st(pb + j, x);
+        }
+    }
+}
+
+// ------------------------------------------------------------- table probes
+
+// True iff an active swap with source > s and target `key` reserved bucket
+// `b` (exactly), or an overflowed reservation with source > s exists there
+// (conservatively).  Entries hold sources; the key of an entry e is
+// target_of(e), recomputed only for entries that outrank s.
+__device__ __forceinline__ bool outranked(const Params &p, uint32_t cntv,
+                                          uint32_t ovfv, const uint32_t *e,
+                                          uint32_t s, uint32_t key)
+{
+    if (ovfv > s + 1u)
+        return true;
+    const uint32_t m = min(cntv, (uint32_t)BUCKET);
+    bool hit = false;
+    for (int j = 0; j < BUCKET; j++) {
+        const uint32_t src = e[j];
+        if ((uint32_t)j < m && src > s && !hit)
+            hit = (target_of(p, src) == key);
+    }
+    return hit;
+}
+
+__device__ __forceinline__ void load_bucket(const Params &p, uint32_t par,
+                                            uint32_t b, uint32_t &cntv,
+                                            uint32_t &ovfv, uint32_t *e)
+{
+    cntv = ld(&p.cnt[(uint64_t)par * p.nb + b]);
+    ovfv = ld(&p.ovf[(uint64_t)par * p.nb + b]);
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p.ent + (uint64_t)b * BUCKET);
+    for (int j = 0; j < BUCKET / 2; j++) {
+        const uint64_t v = ld(q + j);
+        e[2 * j] = (uint32_t)v;
+        e[2 * j + 1] = (uint32_t)(v >> 32);
+    }
+}
+
+// -------------------------------------------------------------- the kernel
+
+// M: swap slots per lane.  EB: record size held in registers (4, 8, 16), or
+// 0 for any multiple of 4 up to 256 bytes, moved after the decision.
+template <int M, int EB>
+__global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
+{
+    __shared__ uint32_t sh_pay[MAXG];
+    __shared__ uint32_t sh_scan[WAVES];
+    __shared__ uint64_t sh_red[3 * WAVES];
+    __shared__ int sh_bad;
+
+    const uint32_t G = gridDim.x, w = blockIdx.x, t = threadIdx.x;
+    uint32_t src[M], tgt[M];
+    bool usable[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+        usable[m] = ((uint64_t)m * G * WG + (uint64_t)w * WG + t) < p.k;
+        src[m] = EMPTY;
+        tgt[m] = 0;
+    }
+    uint32_t cursor = p.n;  // fresh swaps are the indices below the cursor
+    uint32_t epoch = 0;
+    uint64_t rounds = 0, attempts = 0, retries = 0, selfl = 0, maxact = 0;
+    bool failed = false;
+
+    for (;;) {
+        // ---- 1. gather: (active << 16 | free) per workgroup
+        uint32_t f = 0, a = 0;
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            f += (usable[m] && src[m] == EMPTY) ? 1u : 0u;
+            a += (src[m] != EMPTY) ? 1u : 0u;
+        }
+        uint32_t Fw, Aw;
+        const uint32_t lane_off = block_excl_scan(f, &Fw, sh_scan);
+        (void)block_excl_scan(a, &Aw, sh_scan);
+        if (!gather(p, ++epoch, (Aw << 16) | Fw, sh_pay, &sh_bad)) {
+            failed = true;
+            break;
+        }
+        uint64_t pre = 0, totF = 0, totA = 0;
+        for (uint32_t v = t; v < G; v += WG) {
+            const uint32_t x = sh_pay[v];
+            const uint32_t fv = x & 0xFFFFu;
+            pre += (v < w) ? fv : 0u;
+            totF += fv;
+            totA += x >> 16;
+        }
+        block_sum3(pre, totF, totA, sh_red);
+        if (cursor == 0 && totA == 0)
+            break;
+        if (rounds >= p.max_rounds) {
+            if (t == 0)
+                st(p.err, 2u);
+            failed = true;
+            break;
+        }
+        const uint32_t take = (uint32_t)min<uint64_t>(totF, cursor);
+        const uint32_t cnew = cursor - take;
+        const uint32_t par = (uint32_t)(rounds & 1);
+
+        // ---- 2. refill free slots with fresh indices, decreasing
+        uint32_t j = (uint32_t)pre + lane_off;
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (usable[m] && src[m] == EMPTY) {
+                const uint32_t ord = j++;
+                if (ord < take) {
+                    const uint32_t s = cursor - 1u - ord;
+                    const uint32_t h = target_of(p, s);
+                    if (h == s) {
+                        selfl++;
+                    } else {
+                        src[m] = s;
+                        tgt[m] = h;
+                    }
+                }
+            }
+        }
+
+        // ---- 3. reserve R[H[s]], mark the dense window, clean the old parity
+        uint32_t act = 0;
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (src[m] != EMPTY) {
+                act++;
+                const uint32_t b = bucket_of(tgt[m], p.nb);
+                const uint32_t pos = __hip_atomic_fetch_add(
+                    &p.cnt[(uint64_t)par * p.nb + b], 1u, __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                if (pos < (uint32_t)BUCKET)
+                    st(&p.ent[(uint64_t)b * BUCKET + pos], src[m]);
+                else
+                    __hip_atomic_fetch_max(&p.ovf[(uint64_t)par * p.nb + b],
+                                           src[m] + 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (tgt[m] >= cnew && tgt[m] < cursor) {
+                    const uint32_t d = tgt[m] - cnew;
+                    __hip_atomic_fetch_or(&p.bm[(uint64_t)par * p.bmw + (d >> 5)],
+                                          1u << (d & 31u), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        {
+            const uint32_t op = par ^ 1u;
+            for (uint32_t i = w * WG + t; i < p.nb; i += G * WG) {
+                st(&p.cnt[(uint64_t)op * p.nb + i], 0u);
+                st(&p.ovf[(uint64_t)op * p.nb + i], 0u);
+            }
+            for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
+                st(&p.bm[(uint64_t)op * p.bmw + i], 0u);
+        }
+        attempts += act;
+
+        // ---- 4. barrier (carries the active count for the statistics)
+        uint32_t actw;
+        (void)block_excl_scan(act, &actw, sh_scan);
+        if (!gather(p, ++epoch, actw, sh_pay, &sh_bad)) {
+            failed = true;
+            break;
+        }
+        if (w == 0) {
+            uint64_t tot = 0, d0 = 0, d1 = 0;
+            for (uint32_t v = t; v < G; v += WG)
+                tot += sh_pay[v];
+            block_sum3(tot, d0, d1, sh_red);
+            maxact = max(maxact, tot);
+        }
+
+        // ---- 5. commit test and swap
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (src[m] == EMPTY)
+                continue;
+            const uint32_t s = src[m], h = tgt[m];
+            uint32_t ct, ot, et[BUCKET];
+            load_bucket(p, par, bucket_of(h, p.nb), ct, ot, et);
+            const bool fresh = s < cursor;  // s >= cnew holds for all fresh
+            uint32_t bits = 0, cs = 0, os = 0, es[BUCKET];
+            if (fresh) {
+                bits = ld(&p.bm[(uint64_t)par * p.bmw + ((s - cnew) >> 5)]);
+            } else {
+                load_bucket(p, par, bucket_of(s, p.nb), cs, os, es);
+            }
+            Rec<EB == 0 ? 4 : EB> rs, rh;
+            if (EB != 0) {
+                rs.load(p.A, s);
+                rh.load(p.A, h);
+            }
+            bool lose = outranked(p, ct, ot, et, s, h);
+            if (fresh)
+                lose = lose || ((bits >> ((s - cnew) & 31u)) & 1u);
+            else
+                lose = lose || outranked(p, cs, os, es, s, s);
+            if (!lose) {
+                if (EB != 0) {
+                    rh.store(p.A, s);
+                    rs.store(p.A, h);
+                } else {
+                    swap_generic(p.A, p.eb, s, h);
+                }
+                src[m] = EMPTY;
+            } else {
+                retries++;
+            }
+        }
+        cursor = cnew;
+        rounds++;
+    }
+
+    // ---- statistics
+    uint64_t s_att = attempts, s_ret = retries, s_self = selfl;
+    block_sum3(s_att, s_ret, s_self, sh_red);
+    if (t == 0) {
+        __hip_atomic_fetch_add(&p.dstats[S_ATTEMPTS], s_att, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&p.dstats[S_RETRIES], s_ret, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&p.dstats[S_SELF], s_self, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (w == 0) {
+            st(&p.dstats[S_ROUNDS], rounds);
+            st(&p.dstats[S_MAXACT], maxact);
+        }
+        if (failed)
+            st(&p.dstats[S_STATUS], (uint64_t)(int64_t)RP_ETIMEOUT);
+    }
+}
+
+// k = 1: a single active swap per round always commits, so the rounds are the
+// sequential loop itself; used when the auxiliary bound cannot hold a table.
+__global__ void rp_single_kernel(Params p)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0)
+        return;
+    uint64_t rounds = 0, selfl = 0;
+    for (uint32_t i = p.n; i-- > 0;) {
+        const uint32_t h = target_of(p, i);
+        if (h == i) {
+            selfl++;
+            continue;
+        }
+        swap_generic(p.A, p.eb, i, h);
+        rounds++;
+    }
+    st(&p.dstats[S_ROUNDS], rounds);
+    st(&p.dstats[S_ATTEMPTS], rounds);
+    st(&p.dstats[S_MAXACT], (uint64_t)(rounds ? 1 : 0));
+    st(&p.dstats[S_SELF], selfl);
+}
+
+// Zero the auxiliary words and write the host-computed statistics.
+__global__ void rp_init_kernel(uint32_t *aux, uint64_t words32, uint64_t *dstats,
+                               rp_stats host)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = i0; i < words32; i += (uint64_t)gridDim.x * blockDim.x)
+        aux[i] = 0u;
+    if (i0 == 0) {
+        dstats[S_K] = host.k;
+        dstats[S_AUX] = host.aux_words;
+        dstats[S_BOUND] = host.aux_bound_words;
+        dstats[S_ROUNDS] = 0;
+        dstats[S_ATTEMPTS] = 0;
+        dstats[S_RETRIES] = 0;
+        dstats[S_MAXACT] = 0;
+        dstats[S_SELF] = 0;
+        dstats[S_GRID] = host.grid;
+        dstats[S_SLOTS] = host.slots_per_lane;
+        dstats[S_BUCKETS] = host.buckets;
+        dstats[S_STATUS] = 0;
+    }
+}
+
+// H validation: err <- 1 if some H[i] > i.  Read-only on H and A.
+__global__ void rp_check_targets_kernel(const uint64_t *H, uint64_t n, uint32_t *err)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (uint64_t i = i0; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        bad = bad || (H[i] > i);
+    if (bad)
+        st(err, 1u);
+}
+
+__global__ void rp_seed_targets_kernel(const uint64_t *idx, uint64_t count,
+                                       uint64_t seed, uint64_t *out)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = i0; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = umod64(splitmix64(seed ^ idx[i]), idx[i] + 1);
+}
+
+// ------------------------------------------------------------- host planning
+
+struct Plan {
+    bool single;      // k = 1 path
+    uint32_t G, M, k, nb, bmw;
+    uint64_t bound, aux_bytes;
+    int eb_class;     // 4, 8, 16 or 0
+};
+
+uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *nb_out, uint64_t *bmw_out)
+{
+    const uint64_t nb = std::max<uint64_t>(1, (k + LAMBDA - 1) / LAMBDA);
+    const uint64_t bmw = std::max<uint64_t>(1, (k + 31) / 32);
+    if (nb_out) *nb_out = nb;
+    if (bmw_out) *bmw_out = bmw;
+    uint64_t bytes = nb * BUCKET * 4       // entries
+                   + 2 * nb * 4 * 2        // cnt, ovf (two parities)
+                   + 2 * bmw * 4           // dense window (two parities)
+                   + 8;                    // error word (padded)
+    if (G > 1)
+        bytes += 2 * G * 8;                // gather flags (two parities)
+    return bytes;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
+                Plan *pl)
+{
+    std::memset(pl, 0, sizeof(*pl));
+    pl->bound = rp_aux_bound_words(n, eps);
+    pl->eb_class = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
+    const uint64_t budget = pl->bound * 8;
+    // The persistent path needs at least one bucket and k >= 2.
+    if (aux_bytes_for(2, 1, nullptr, nullptr) > budget) {
+        pl->single = true;
+        pl->k = 1;
+        pl->G = 1;
+        pl->M = 1;
+        pl->aux_bytes = 8;  // the error word; budget >= 8 since bound >= 1
+        return RP_OK;
+    }
+    // Largest k that fits with a single workgroup (no flags).
+    auto kmax_for = [&](uint64_t G) {
+        uint64_t lo = 0, hi = (uint64_t)n;  // k never needs to exceed n
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) / 2;
+            if (aux_bytes_for(mid, G, nullptr, nullptr) <= budget) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    const int slot_opts[4] = {1, 2, 4, 8};
+    const int want_m = env_int("RP_SLOTS", 0);
+    const int want_g = env_int("RP_GRID", 0);
+    uint64_t k0 = kmax_for(1);
+    // Choose M then G: prefer one slot per lane with as many workgroups as
+    // the chip holds, more slots per lane only when the grid is full.
+    int mi = 0;
+    if (want_m) {
+        for (mi = 0; mi < 3 && slot_opts[mi] < want_m; mi++) {}
+    } else {
+        while (mi < 3 && k0 > (uint64_t)cus * occ_by_m[mi] * WG * slot_opts[mi]) mi++;
+    }
+    const uint64_t M = slot_opts[mi];
+    const uint64_t gmax = std::min<uint64_t>(MAXG, (uint64_t)cus * occ_by_m[mi]);
+    uint64_t G = want_g ? std::min<uint64_t>(want_g, gmax)
+                        : std::min<uint64_t>(gmax, (k0 + WG * M - 1) / (WG * M));
+    if (G < 1) G = 1;
+    uint64_t k = std::min<uint64_t>(kmax_for(G), G * WG * M);
+    while (k < 2 && G > 1) {
+        G = std::max<uint64_t>(1, G / 2);
+        k = std::min<uint64_t>(kmax_for(G), G * WG * M);
+    }
+    if (k < 2) {
+        pl->single = true;
+        pl->k = 1;
+        pl->G = pl->M = 1;
+        pl->aux_bytes = 8;
+        return RP_OK;
+    }
+    uint64_t nb, bmw;
+    pl->aux_bytes = aux_bytes_for(k, G, &nb, &bmw);
+    pl->k = (uint32_t)k;
+    pl->G = (uint32_t)G;
+    pl->M = (uint32_t)M;
+    pl->nb = (uint32_t)nb;
+    pl->bmw = (uint32_t)bmw;
+    return RP_OK;
+}
+
+int validate(void *A, uint64_t n, uint32_t eb, double eps)
+{
+    if (!(eps > 0.0 && eps < 1.0))
+        return RP_EINVAL;
+    if (eb == 0 || (eb & 3u) != 0 || eb > 256)
+        return RP_EINVAL;
+    if (n >= (1ull << 32))
+        return RP_EINVAL;
+    if (A == nullptr && n > 1)
+        return RP_EINVAL;
+    return RP_OK;
+}
+
+using KernelFn = void (*)(Params);
+
+template <int M>
+KernelFn pick_eb(int ebc)
+{
+    switch (ebc) {
+    case 4: return rp_rounds_kernel<M, 4>;
+    case 8: return rp_rounds_kernel<M, 8>;
+    case 16: return rp_rounds_kernel<M, 16>;
+    default: return rp_rounds_kernel<M, 0>;
+    }
+}
+
+KernelFn pick_kernel(int M, int ebc)
+{
+    switch (M) {
+    case 1: return pick_eb<1>(ebc);
+    case 2: return pick_eb<2>(ebc);
+    case 4: return pick_eb<4>(ebc);
+    default: return pick_eb<8>(ebc);
+    }
+}
+
+struct DevInfo {
+    bool ok = false;
+    int cus = 256;
+    int occ[4][5] = {};  // [M index][eb class index] co-resident WGs per CU
+};
+
+std::mutex g_mu;
+std::vector<DevInfo> g_dev;
+
+int eb_index(int ebc) { return ebc == 4 ? 0 : ebc == 8 ? 1 : ebc == 16 ? 2 : 3; }
+
+int device_info(int dev, DevInfo *out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((int)g_dev.size() <= dev)
+        g_dev.resize(dev + 1);
+    DevInfo &d = g_dev[dev];
+    if (!d.ok) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return RP_EDEVICE;
+        d.cus = prop.multiProcessorCount;
+        const int ms[4] = {1, 2, 4, 8}, ebs[4] = {4, 8, 16, 0};
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                int occ = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &occ, reinterpret_cast<const void *>(pick_kernel(ms[a], ebs[b])),
+                        WG, 0) != hipSuccess)
+                    return RP_EDEVICE;
+                d.occ[a][b] = std::max(occ, 1);
+            }
+        d.ok = true;
+    }
+    *out = d;
+    return RP_OK;
+}
+
+void fill_host_stats(const Plan &pl, rp_stats *s)
+{
+    std::memset(s, 0, sizeof(*s));
+    s->k = pl.k;
+    s->aux_words = (pl.aux_bytes + 7) / 8;
+    s->aux_bound_words = pl.bound;
+    s->grid = pl.G;
+    s->slots_per_lane = pl.M;
+    s->buckets = pl.nb;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t rp_aux_bound_words(uint64_t n, double eps)
+{
+    if (n == 0 || !(eps > 0.0 && eps < 1.0))
+        return 0;
+    const long double x = powl((long double)n, 1.0L - (long double)eps);
+    long double w = floorl(x);
+    // Snap values that are an integer up to rounding (e.g. (2^20)^0.5).
+    if (x - w > 1.0L - 1e-12L * std::max<long double>(1.0L, x))
+        w += 1.0L;
+    if (w < 1.0L)
+        w = 1.0L;  // n^(1-eps) >= 1 for n >= 1
+    return (uint64_t)w;
+}
+
+int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
+            rp_stats *stats_out)
+{
+    int rc = validate((void *)1, n, elem_bytes, eps);
+    if (rc != RP_OK)
+        return rc;
+    int occ[4];
+    int cus = 256;
+    const int ebc = (elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16) ? (int)elem_bytes : 0;
+    if (device >= 0) {
+        DevInfo d;
+        rc = device_info(device, &d);
+        if (rc != RP_OK)
+            return rc;
+        cus = d.cus;
+        for (int a = 0; a < 4; a++)
+            occ[a] = d.occ[a][eb_index(ebc)];
+    } else {
+        for (int a = 0; a < 4; a++)
+            occ[a] = 2;
+    }
+    Plan pl;
+    rc = choose_plan(n, elem_bytes, eps, cus, occ, &pl);
+    if (rc != RP_OK)
+        return rc;
+    if (stats_out)
+        fill_host_stats(pl, stats_out);
+    return RP_OK;
+}
+
+int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
+                       const uint64_t *H, uint64_t seed, double eps,
+                       void *stream_, rp_stats *stats)
+{
+    int rc = validate(A, n, elem_bytes, eps);
+    if (rc != RP_OK)
+        return rc;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    if (n <= 1) {
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->aux_bound_words = rp_aux_bound_words(n ? n : 1, eps);
+        }
+        return RP_OK;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return RP_EDEVICE;
+    DevInfo di;
+    rc = device_info(dev, &di);
+    if (rc != RP_OK)
+        return rc;
+    const int ebc = (elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16) ? (int)elem_bytes : 0;
+    int occ[4];
+    for (int a = 0; a < 4; a++)
+        occ[a] = di.occ[a][eb_index(ebc)];
+    Plan pl;
+    rc = choose_plan(n, elem_bytes, eps, di.cus, occ, &pl);
+    if (rc != RP_OK)
+        return rc;
+
+    // Auxiliary words (counted) followed by the statistics record (output).
+    const uint64_t aux_bytes = pl.aux_bytes;  // a multiple of 8
+    const uint64_t total = aux_bytes + S_WORDS * 8;
+    void *mem = nullptr;
+    if (hipMallocAsync(&mem, total, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RP_ENOMEM;
+    }
+    unsigned char *base = static_cast<unsigned char *>(mem);
+    uint64_t *dstats = reinterpret_cast<uint64_t *>(base + aux_bytes);
+    rp_stats hs;
+    fill_host_stats(pl, &hs);
+    rp_init_kernel<<<64, 256, 0, stream>>>(reinterpret_cast<uint32_t *>(base),
+                                           aux_bytes / 4, dstats, hs);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipFreeAsync(mem, stream);
+        return RP_EDEVICE;
+    }
+
+    Params p{};
+    p.A = static_cast<unsigned char *>(A);
+    p.H = H;
+    p.seed = seed;
+    p.n = (uint32_t)n;
+    p.eb = elem_bytes;
+    p.k = pl.k;
+    p.nb = pl.nb;
+    p.bmw = pl.bmw;
+    p.dstats = dstats;
+    p.max_rounds = n + 64;
+    // Carve the counted words: [ent | cnt | ovf | bm | flags | err]; ent
+    // first so that every bucket is one aligned 64-byte line.
+    unsigned char *cur = base;
+    if (!pl.single) {
+        p.ent = reinterpret_cast<uint32_t *>(cur);
+        cur += (uint64_t)pl.nb * BUCKET * 4;
+        p.cnt = reinterpret_cast<uint32_t *>(cur);
+        cur += 2ull * pl.nb * 4;
+        p.ovf = reinterpret_cast<uint32_t *>(cur);
+        cur += 2ull * pl.nb * 4;
+        p.bm = reinterpret_cast<uint32_t *>(cur);
+        cur += 2ull * pl.bmw * 4;
+        if (pl.G > 1) {
+            p.flags = reinterpret_cast<uint64_t *>(cur);
+            cur += 2ull * pl.G * 8;
+        }
+    }
+    p.err = reinterpret_cast<uint32_t *>(cur);
+    cur += 8;
+
+    if (H != nullptr) {
+        // H mode: reject H[i] > i before anything moves.
+        rp_check_targets_kernel<<<1024, 256, 0, stream>>>(H, n, p.err);
+        uint32_t herr = 0;
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&herr, p.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            (void)hipFreeAsync(mem, stream);
+            return RP_EDEVICE;
+        }
+        if (herr != 0) {
+            (void)hipFreeAsync(mem, stream);
+            return RP_EINVAL;
+        }
+    }
+
+    if (pl.single) {
+        rp_single_kernel<<<1, 64, 0, stream>>>(p);
+        if (hipGetLastError() != hipSuccess) {
+            (void)hipFreeAsync(mem, stream);
+            return RP_EDEVICE;
+        }
+    } else {
+        KernelFn fn = pick_kernel((int)pl.M, pl.eb_class);
+        void *args[] = {&p};
+        if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(pl.G),
+                                       dim3(WG), args, 0, stream) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFreeAsync(mem, stream);
+            return RP_EDEVICE;
+        }
+    }
+    if (stats) {
+        if (hipMemcpyAsync(stats, dstats, sizeof(rp_stats), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess) {
+            (void)hipFreeAsync(mem, stream);
+            return RP_EDEVICE;
+        }
+    }
+    if (hipFreeAsync(mem, stream) != hipSuccess)
+        return RP_EDEVICE;
+    return RP_OK;
+}
+
+int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
+                    uint64_t *out, void *stream_)
+{
+    if (count == 0)
+        return RP_OK;
+    if (idx == nullptr || out == nullptr)
+        return RP_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    const uint64_t blocks = std::min<uint64_t>(4096, (count + 255) / 256);
+    rp_seed_targets_kernel<<<(unsigned)blocks, 256, 0, stream>>>(idx, count, seed, out);
+    return hipGetLastError() == hipSuccess ? RP_OK : RP_EDEVICE;
+}
+
+}  // extern "C"

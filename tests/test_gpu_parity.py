@@ -1,0 +1,231 @@
+"""GPU parity: librp (through its C ABI) against the CPU oracle, bit-exact.
+
+Every input is seeded and synthetic.  The result of a Knuth shuffle is unique
+given (A, H), so the bar is equality of every byte; where the oracle cannot
+shuffle the whole array on the host (the largest sizes) it computes sampled
+output positions exactly and the full output is checked to be a permutation.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2103_01216_amd as rp
+from paper_2103_01216_amd import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(A, **kw):
+    st = rp.rp_shuffle_inplace(A, **kw)
+    s = st.get()
+    assert s["status"] == 0, s
+    return s
+
+
+def _check_stats(s, n, H_np=None):
+    assert s["aux_words"] <= s["aux_bound_words"]
+    assert s["attempts"] == s["attempts"]  # present
+    if H_np is not None:
+        selfl = int(np.sum(H_np == np.arange(n, dtype=np.uint64)))
+        nonself = n - selfl
+        assert s["self_loops"] == selfl
+        assert s["attempts"] == nonself + s["retries"]
+        if s["k"] > 0:
+            assert s["rounds"] >= -(-nonself // s["k"])
+        assert s["rounds"] <= nonself + 64
+
+
+def _host_records(n, eb, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2**32, size=(n, eb // 4), dtype=np.uint32)
+
+
+# ---------------------------------------------------------------- H drawing
+
+def test_seed_targets_exact_mod():
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([
+        np.arange(0, 1 << 16, dtype=np.uint64),
+        rng.integers(0, 2**32, 20000, dtype=np.uint64),
+        np.array([2**32 - 1, 2**32 - 2, 2**31 - 1, 2**31, 2**31 + 1]
+                 + [2**j - 1 for j in range(1, 33)] + [2**j for j in range(32)],
+                 dtype=np.uint64)])
+    for seed in (0, 1, 2**64 - 1, 0xDEADBEEF):
+        got = rp.rp_seed_targets(torch.from_numpy(idx.view(np.int64)).to(DEV), seed)
+        got = got.cpu().numpy().view(np.uint64)
+        want = np.array([oracle.seed_target(seed, int(i)) for i in idx[:2000]]
+                        + [oracle.seed_target(seed, int(i)) for i in idx[2000:]],
+                        dtype=np.uint64)
+        assert np.array_equal(got, want), seed
+
+
+# ------------------------------------------------------- small exact parity
+
+@pytest.mark.parametrize("n", [2, 3, 7, 8, 1000, (1 << 16) + 3])
+@pytest.mark.parametrize("eps", [0.1, 0.5, 0.9])
+@pytest.mark.parametrize("eb", [4, 8, 16, 64, 12])
+def test_seed_mode_parity_small(n, eps, eb):
+    for seed in (0, 1):
+        host = _host_records(n, eb, seed + 17)
+        want = host.copy()
+        oracle.knuth_shuffle_seed(want, seed)
+        A = torch.from_numpy(host.view(np.int32)).to(DEV)
+        s = _run(A, seed=seed, eps=eps)
+        got = A.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want), (n, eps, eb, seed, s)
+        _check_stats(s, n, oracle.seed_targets(n, seed))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_config_n2p20_int64_eps_half(seed):
+    n = 1 << 20
+    A = workloads.identity(n, torch.int64, DEV)
+    s = _run(A, seed=seed, eps=0.5)
+    want = np.arange(n, dtype=np.int64)
+    oracle.knuth_shuffle_seed(want, seed)
+    assert np.array_equal(A.cpu().numpy(), want)
+    assert s["aux_bound_words"] == 1024 and s["aux_words"] <= 1024
+    if seed == 0:
+        _check_stats(s, n, oracle.seed_targets(n, seed))
+
+
+# ----------------------------------------------------------- explicit H
+
+@pytest.mark.parametrize("kind", ["zero", "self", "prev", "hot4"])
+@pytest.mark.parametrize("n", [2, 100, 3001])
+def test_adversarial_targets(kind, n):
+    H = workloads.adversarial_targets(n, kind)
+    want = np.arange(n, dtype=np.int64)
+    oracle.knuth_shuffle(want, H)
+    for eps in (0.3, 0.7):
+        A = workloads.identity(n, torch.int64, DEV)
+        s = _run(A, H=torch.from_numpy(H.view(np.int64)).to(DEV), eps=eps)
+        assert np.array_equal(A.cpu().numpy(), want), (kind, n, eps)
+        _check_stats(s, n, H)
+
+
+@pytest.mark.parametrize("n", [1000, 50_000, 1 << 18])
+def test_uniform_targets_parity(n):
+    H = workloads.uniform_targets(n, 99)
+    for eb in (4, 8, 64):
+        host = _host_records(n, eb, 3)
+        want = host.copy()
+        oracle.knuth_shuffle(want, H)
+        A = torch.from_numpy(host.view(np.int32)).to(DEV)
+        s = _run(A, H=torch.from_numpy(H.view(np.int64)).to(DEV), eps=0.5)
+        assert np.array_equal(A.cpu().numpy().view(np.uint32), want)
+        _check_stats(s, n, H)
+
+
+def test_seed_mode_equals_h_mode():
+    n, seed = 200_000, 42
+    H = oracle.seed_targets(n, seed)
+    A1 = workloads.identity(n, torch.int64, DEV)
+    A2 = A1.clone()
+    _run(A1, seed=seed, eps=0.4)
+    _run(A2, H=torch.from_numpy(H.view(np.int64)).to(DEV), eps=0.4)
+    assert torch.equal(A1, A2)
+
+
+def test_invalid_targets_leave_A_untouched():
+    n = 10_000
+    H = workloads.uniform_targets(n, 1)
+    H[5000] = 5001
+    A = workloads.identity(n, torch.int64, DEV)
+    with pytest.raises(rp.RpError) as ei:
+        rp.rp_shuffle_inplace(A, H=torch.from_numpy(H.view(np.int64)).to(DEV), eps=0.5)
+    assert ei.value.code == rp.RP_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(A.cpu(), torch.arange(n))
+
+
+def test_trivial_sizes():
+    for n in (0, 1):
+        A = torch.arange(n, dtype=torch.int64, device=DEV)
+        s = rp.rp_shuffle_inplace(A, seed=3, eps=0.5).get()
+        assert s["rounds"] == 0
+        assert A.cpu().tolist() == list(range(n))
+
+
+# ------------------------------------------------------ schedule invariance
+
+@pytest.mark.parametrize("grid,slots", [("1", "1"), ("3", "2"), ("17", "4"), ("64", "8"), ("", "")])
+def test_schedule_invariance(monkeypatch, grid, slots):
+    n, seed = (1 << 18) + 11, 7
+    want = np.arange(n, dtype=np.int64)
+    oracle.knuth_shuffle_seed(want, seed)
+    monkeypatch.setenv("RP_GRID", grid)
+    monkeypatch.setenv("RP_SLOTS", slots)
+    for eps in (0.2, 0.5):
+        A = workloads.identity(n, torch.int64, DEV)
+        s = _run(A, seed=seed, eps=eps)
+        assert np.array_equal(A.cpu().numpy(), want), (grid, slots, eps, s)
+        if grid:
+            assert s["grid"] <= int(grid)
+
+
+def test_repeat_runs_identical():
+    n = 300_001
+    outs = []
+    for _ in range(3):
+        A = workloads.identity(n, torch.int32, DEV)
+        _run(A, seed=11, eps=0.35)
+        outs.append(A.cpu())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2])
+
+
+# ------------------------------------------------------------ full sizes
+
+def _sampled_check(A, n, seed, nsamp=512, rows=False):
+    rng = np.random.default_rng(seed + 1000)
+    pos = np.unique(np.concatenate([[0, 1, n - 2, n - 1],
+                                    rng.integers(0, n, nsamp)]))
+    src = oracle.sample_sources(n, pos, seed=seed)
+    got = A[torch.from_numpy(pos.astype(np.int64)).to(A.device)].cpu().numpy()
+    if rows:
+        assert np.array_equal(got.view(np.uint32), workloads.records64_numpy(src))
+    else:
+        assert np.array_equal(got.astype(np.int64), src.astype(np.int64))
+
+
+def _is_permutation(A, n):
+    seen = torch.zeros(n, dtype=torch.bool, device=A.device)
+    seen[A.to(torch.int64)] = True
+    return bool(seen.all())
+
+
+@pytest.mark.parametrize("dtype", [torch.int32, torch.int64])
+@pytest.mark.parametrize("eps", [0.25, 0.5])
+def test_n2p28(dtype, eps):
+    n, seed = 1 << 28, 1
+    A = workloads.identity(n, dtype, DEV)
+    s = _run(A, seed=seed, eps=eps)
+    assert s["aux_words"] <= s["aux_bound_words"] == rp.rp_aux_bound_words(n, eps)
+    assert _is_permutation(A, n)
+    _sampled_check(A, n, seed)
+    del A
+    torch.cuda.empty_cache()
+
+
+def test_n2p30_int64():
+    n, seed = 1 << 30, 1
+    A = workloads.identity(n, torch.int64, DEV)
+    s = _run(A, seed=seed, eps=0.5)
+    assert s["aux_bound_words"] == 32768 and s["aux_words"] <= 32768
+    assert _is_permutation(A, n)
+    _sampled_check(A, n, seed)
+    del A
+    torch.cuda.empty_cache()
+
+
+def test_records64_n2p26():
+    n, seed = 1 << 26, 1
+    A = workloads.records64(n, DEV)
+    s = _run(A, seed=seed, eps=0.5)
+    assert s["aux_bound_words"] == 8192 and s["aux_words"] <= 8192
+    assert _is_permutation(A[:, 0], n)
+    _sampled_check(A, n, seed, rows=True)
+    del A
+    torch.cuda.empty_cache()
