@@ -21,36 +21,41 @@
 //   2. refill   free slots take fresh indices (decreasing), H[s] is computed
 //               (seed mode) or read; self-loops retire at once (Section 4.1
 //               removes them; a swap with H[s] = s is a no-op);
-//   3. reserve  each active swap adds itself to the bucket of key H[s] in
-//               the slot table (the priority write: the largest source, i.e.
-//               the earliest swap in sequential order, is the one that
-//               wins), and sets bit H[s] of the dense window if H[s] lies in
-//               this round's fresh range;
+//   3. reserve  each active swap adds an entry for key H[s] to the slot
+//               table, and sets bit H[s] of the dense window when H[s] lies
+//               in it;
 //   4. barrier
-//   5. commit   swap s wins iff no active swap with a larger source targets
-//               H[s] (bucket of H[s]) and no active swap targets s (dense
-//               window bit for fresh sources, bucket of s otherwise); this is
-//               the single-reservation test of Appendix A.2.  Winners swap
-//               A[s] and A[H[s]]; losers stay in their slots for the next
-//               round (the paper's pack step becomes a per-workgroup prefix
-//               sum over free slots in step 1).
-// Tables are double-buffered by round parity and the stale parity is cleared
-// during step 3, which is the cleaning phase of Appendix A.1.
+//   5. commit   swap s wins iff no active swap with a larger source (earlier
+//               in the sequential order) targets H[s] (table lookup) and no
+//               active swap targets s (dense window bit; table lookup for the
+//               rare source outside the window) -- the single-reservation
+//               test of Appendix A.2, with the priority write resolved at
+//               read time.  Winners swap A[s] and A[H[s]]; losers stay in
+//               their slots for the next round (the paper's pack step becomes
+//               the per-workgroup prefix sum over free slots in step 1).
+// The table headers and the dense window are double-buffered by round parity
+// and the stale parity is cleared during step 3: the cleaning phase of
+// Appendix A.1.
 //
-// Slot table layout (all 32-bit words, device memory):
-//   ent[b * C + j]      j < C: source index of the j-th swap that reserved
-//                       bucket b this round (key implicit: H[source])
-//   cnt[par * nb + b]   number of reservations into bucket b this round
-//   ovf[par * nb + b]   1 + largest source whose reservation found bucket b
-//                       full (0 = none); such a bucket makes every
-//                       lower-priority swap on it lose, which is exact-safe
-//   bm[par * bmw + i]   dense window bits: bit x set iff some active swap
-//                       targets cursor_new + x
-// Cross-workgroup data is accessed only with relaxed agent-scope atomic loads
-// and stores (device-coherent, never a stale cache hit); a workgroup waits
-// for all of its memory operations to complete before it publishes its
-// barrier flag, and every access after a barrier is issued after the flags
-// were observed.
+// Auxiliary layout (device memory, every byte counted against the bound):
+//   ent[b * 32 + j]     bucket b: 32 entries of 32 bits (one 128-byte block);
+//                       entry = fingerprint(key):6 | (source - base):26
+//   hdr[par * nb + b]   64 bits: low = reservations that tried bucket b this
+//                       round, high = 1 + largest source whose reservation
+//                       could not be placed (0 = none)
+//   bm[par * bmw + i]   dense window: bit x set iff an active swap targets
+//                       base + x, for x < 32 * bmw (at least 2k)
+//   flags[par * G + w]  gather flags: epoch:32 | payload:32
+//   err                 watchdog / error word
+// RP-Final keeps R for the round's consecutive keys in a prefix-sized array;
+// here that array holds one bit per key, because the commit test only asks
+// whether any other active swap targets the source.
+//
+// Cross-workgroup data is accessed only with device-coherent operations:
+// relaxed agent-scope atomics, and 16-byte buffer loads with the device-scope
+// cache policy for table blocks.  A workgroup waits for all of its memory
+// operations to complete before it publishes its barrier flag, and every
+// access after a barrier is issued after the flags were observed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,11 +72,15 @@ namespace {
 
 constexpr int WG = 256;                 // threads per workgroup
 constexpr int WAVES = WG / 64;
-constexpr int BUCKET = 16;              // entries per bucket (one 64-byte line)
-constexpr int LAMBDA = 8;               // target reservations per bucket
+constexpr int BUCKET = 32;              // entries per bucket (128 bytes)
+constexpr int LAMBDA = 14;              // target reservations per bucket
+constexpr int SPILL = 4;                // buckets a reservation may try
+constexpr uint32_t OFFB = 26;           // entry = fingerprint:6 | offset:26
+constexpr uint32_t OFFMASK = (1u << OFFB) - 1u;
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int MAXG = 2048;              // largest grid the gather supports
 constexpr uint64_t WATCHDOG_TICKS = 500000000ull;  // 5 s at 100 MHz
+constexpr int SC1 = 16;                 // cache policy: device scope
 
 struct Params {
     unsigned char *A;
@@ -80,11 +89,10 @@ struct Params {
     uint32_t n;
     uint32_t eb;
     uint32_t k;
-    uint32_t nb;
-    uint32_t bmw;
+    uint32_t nb;         // buckets
+    uint32_t bmw;        // dense-window words per parity
     uint32_t *ent;
-    uint32_t *cnt;
-    uint32_t *ovf;
+    uint64_t *hdr;
     uint32_t *bm;
     uint64_t *flags;
     uint32_t *err;
@@ -111,10 +119,22 @@ __device__ __forceinline__ void st(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Reset a word that is otherwise only updated by read-modify-write atomics.
+// It must be written by an atomic RMW too: on gfx950 the RMW atomics and a
+// plain device-scope store to the same word are not ordered with each other,
+// and a store-based reset was observed to be lost.
+__device__ __forceinline__ void clear_rmw(uint32_t *p)
+{
+    (void)__hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void wait_mem()
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
+
+__device__ __forceinline__ uint32_t *hdr_cnt(uint64_t *h) { return reinterpret_cast<uint32_t *>(h); }
+__device__ __forceinline__ uint32_t *hdr_ovf(uint64_t *h) { return reinterpret_cast<uint32_t *>(h) + 1; }
 
 // ------------------------------------------------------- exact integer math
 
@@ -169,123 +189,70 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t nb)
     return (uint32_t)(((uint64_t)h * nb) >> 32);
 }
 
-// ----------------------------------------------------- workgroup reductions
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+__device__ __forceinline__ uint32_t fingerprint(uint32_t key)
 {
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
+    return (uint32_t)(((uint64_t)key * 0xD6E8FEB86659FD93ull) >> 58);
 }
+
+// ----------------------------------------------------------- wave helpers
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
     const int lane = threadIdx.x & 63;
+#pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        uint32_t u = __shfl_up(v, o, 64);
+        const uint32_t u = __shfl_up(v, o, 64);
         if (lane >= o)
             v += u;
     }
     return v;
 }
 
-// Exclusive prefix of v over the workgroup; *total gets the sum.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total,
-                                                    uint32_t *sh)
-{
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t incl = wave_incl_scan(v);
-    __syncthreads();
-    if (lane == 63)
-        sh[wave] = incl;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-    for (int i = 0; i < WAVES; i++) {
-        const uint32_t x = sh[i];
-        base += (i < wave) ? x : 0;
-        tot += x;
-    }
-    *total = tot;
-    return base + incl - v;
-}
-
-// Sum of a, b, c over the workgroup (uniform result).
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 {
+#pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         v += __shfl_xor(v, o, 64);
     return v;
 }
 
-__device__ __forceinline__ void block_sum3(uint64_t &a, uint64_t &b, uint64_t &c,
-                                           uint64_t *sh)
-{
-    a = wave_sum64(a);
-    b = wave_sum64(b);
-    c = wave_sum64(c);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) {
-        sh[3 * wave] = a;
-        sh[3 * wave + 1] = b;
-        sh[3 * wave + 2] = c;
-    }
-    __syncthreads();
-    a = b = c = 0;
-    for (int i = 0; i < WAVES; i++) {
-        a += sh[3 * i];
-        b += sh[3 * i + 1];
-        c += sh[3 * i + 2];
-    }
-    __syncthreads();
-}
-
 // --------------------------------------------------------------- the gather
 
-// Publish `payload` under `epoch` and collect every workgroup's payload for
-// the same epoch into sh_pay[0..G).  Doubles as the grid barrier: it returns
-// only after every workgroup published, and this workgroup's memory
-// operations complete before its flag is written.  Flags are double-buffered
+// Wave 0 of every workgroup: publish `payload` under `epoch`, wait for every
+// workgroup's flag of the same epoch and return, per lane, the payloads of
+// workgroups lane, lane+64, ... through `visit`.  Flags are double-buffered
 // by epoch parity: a workgroup cannot publish epoch e+2 before every
 // workgroup has read epoch e.  Returns false when the watchdog fired.
-__device__ bool gather(const Params &p, uint32_t epoch, uint32_t payload,
-                       uint32_t *sh_pay, int *sh_bad)
+// The caller has made this workgroup's memory operations complete (wait_mem
+// in every wave, then a workgroup barrier) before calling.
+template <typename Visit>
+__device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t epoch,
+                                             uint32_t payload, Visit visit)
 {
-    const uint32_t G = gridDim.x;
-    wait_mem();
-    if (threadIdx.x == 0)
-        *sh_bad = 0;
-    __syncthreads();
-    if (G == 1) {
-        if (threadIdx.x == 0)
-            sh_pay[0] = payload;
-        __syncthreads();
-        return true;
-    }
+    const uint32_t G = gridDim.x, lane = threadIdx.x & 63;
     uint64_t *fl = p.flags + (uint64_t)(epoch & 1u) * G;
-    if (threadIdx.x == 0)
+    if (lane == 0)
         st(&fl[blockIdx.x], ((uint64_t)epoch << 32) | payload);
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    bool bad = false;
-    for (uint32_t v = threadIdx.x; v < G && !bad; v += WG) {
+    bool ok = true;
+    for (uint32_t v = lane; v < G; v += 64) {
         uint64_t f = ld(&fl[v]);
         while ((uint32_t)(f >> 32) != epoch) {
             if (__builtin_amdgcn_s_memrealtime() - t0 > WATCHDOG_TICKS ||
                 ld(p.err) != 0u) {
                 st(p.err, 1u);
-                bad = true;
+                ok = false;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             f = ld(&fl[v]);
         }
-        sh_pay[v] = (uint32_t)f;
+        if (!ok)
+            break;
+        visit(v, (uint32_t)f);
     }
-    if (bad)
-        *sh_bad = 1;
     asm volatile("" ::: "memory");
-    __syncthreads();
-    return *sh_bad == 0;
+    return __all(ok);
 }
 
 // ------------------------------------------------------------ record moves
@@ -332,8 +299,10 @@ __device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
         for (uint32_t j = 0; j < eb / 8; j += 4) {
             uint64_t x[4], y[4];
             const uint32_t m = min(4u, eb / 8 - j);
+#pragma unroll
             for (uint32_t u = 0; u < 4; u++)
                 if (u < m) { x[u] = ld(pa + j + u); y[u] = ld(pb + j + u); }
+#pragma unroll
             for (uint32_t u = 0; u < 4; u++)
                 if (u < m) { st(pa + j + u, y[u]); st(pb + j + u, x[u]); }
         }
@@ -348,39 +317,112 @@ __device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
     }
 }
 
-// ------------------------------------------------------------- table probes
+// ------------------------------------------------------------- slot table
+//
+// A reservation of swap s on key x is one 32-bit entry in bucket
+// bucket_of(x): the 6-bit fingerprint of x and s - base, where base is the
+// round's lowest possible active source (the new cursor).  It goes into the
+// first of buckets b, b+1, ..., b+SPILL-1 (mod nb) whose counter (one atomic
+// add) shows a free entry.  A bucket's counter counts every attempt on it,
+// so "count <= BUCKET" proves that no reservation moved on from it.  A
+// reservation that finds SPILL full buckets, or whose offset does not fit in
+// 26 bits, raises the overflow word of its home bucket to s + 1 instead,
+// which makes every swap with a smaller source on that bucket lose (safe;
+// the sizes keep it vanishingly rare).  The key of an entry is recomputed
+// only when its fingerprint matches.
 
-// True iff an active swap with source > s and target `key` reserved bucket
-// `b` (exactly), or an overflowed reservation with source > s exists there
-// (conservatively).  Entries hold sources; the key of an entry e is
-// target_of(e), recomputed only for entries that outrank s.
-__device__ __forceinline__ bool outranked(const Params &p, uint32_t cntv,
-                                          uint32_t ovfv, const uint32_t *e,
-                                          uint32_t s, uint32_t key)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load_bucket(__amdgpu_buffer_rsrc_t rs, uint32_t b,
+                                            uint32_t *e)
 {
-    if (ovfv > s + 1u)
-        return true;
-    const uint32_t m = min(cntv, (uint32_t)BUCKET);
-    bool hit = false;
-    for (int j = 0; j < BUCKET; j++) {
-        const uint32_t src = e[j];
-        if ((uint32_t)j < m && src > s && !hit)
-            hit = (target_of(p, src) == key);
+#pragma unroll
+    for (int i = 0; i < BUCKET / 4; i++) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
+            rs, (int)(b * (uint32_t)(BUCKET * 4) + i * 16), 0, SC1);
+        e[4 * i] = v.x;
+        e[4 * i + 1] = v.y;
+        e[4 * i + 2] = v.z;
+        e[4 * i + 3] = v.w;
     }
-    return hit;
 }
 
-__device__ __forceinline__ void load_bucket(const Params &p, uint32_t par,
-                                            uint32_t b, uint32_t &cntv,
-                                            uint32_t &ovfv, uint32_t *e)
+// Bit mask of entries j < min(c, BUCKET) with fingerprint fp whose source
+// outranks (is larger than) base + off_s.
+__device__ __forceinline__ uint32_t candidates(const uint32_t *e, uint32_t c,
+                                               uint32_t fp, uint32_t off_s)
 {
-    cntv = ld(&p.cnt[(uint64_t)par * p.nb + b]);
-    ovfv = ld(&p.ovf[(uint64_t)par * p.nb + b]);
-    const uint64_t *q = reinterpret_cast<const uint64_t *>(p.ent + (uint64_t)b * BUCKET);
-    for (int j = 0; j < BUCKET / 2; j++) {
-        const uint64_t v = ld(q + j);
-        e[2 * j] = (uint32_t)v;
-        e[2 * j + 1] = (uint32_t)(v >> 32);
+    const uint32_t m = min(c, (uint32_t)BUCKET);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int j = 0; j < BUCKET; j++) {
+        const uint32_t x = e[j];
+        const bool hit = (uint32_t)j < m && (x >> OFFB) == fp && (x & OFFMASK) > off_s;
+        mask |= hit ? (1u << j) : 0u;
+    }
+    return mask;
+}
+
+// e[i] for a run-time i without dynamic register indexing (which would move
+// the array to scratch memory).
+__device__ __forceinline__ uint32_t pick(const uint32_t *e, int i)
+{
+    uint32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < BUCKET; j++)
+        x = (j == i) ? e[j] : x;
+    return x;
+}
+
+__device__ __forceinline__ void reserve_finish(const Params &p, uint32_t par,
+                                               uint32_t b, uint32_t pos,
+                                               uint32_t e, uint32_t s)
+{
+    uint32_t bj = b;
+    for (int j = 0;; j++) {
+        if (pos < (uint32_t)BUCKET) {
+            st(&p.ent[(uint64_t)bj * BUCKET + pos], e);
+            return;
+        }
+        if (j + 1 >= SPILL)
+            break;
+        bj = (bj + 1 == p.nb) ? 0u : bj + 1;
+        pos = __hip_atomic_fetch_add(hdr_cnt(&p.hdr[(uint64_t)par * p.nb + bj]), 1u,
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_fetch_max(hdr_ovf(&p.hdr[(uint64_t)par * p.nb + b]), s + 1u,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True iff some active swap with a source larger than s reserved `key` this
+// round (exact), or an overflow on the home bucket forbids s (conservative).
+// h0 and e0 are the home bucket's header and entries, already loaded.
+__device__ __forceinline__ bool outranked(const Params &p, __amdgpu_buffer_rsrc_t rs,
+                                          uint32_t par, uint32_t base, uint32_t s,
+                                          uint32_t key, uint32_t b, uint64_t h0,
+                                          const uint32_t *e0)
+{
+    if ((uint32_t)(h0 >> 32) > s + 1u)
+        return true;
+    const uint32_t fp = fingerprint(key), off_s = s - base;
+    uint32_t cj = (uint32_t)h0, bj = b;
+    uint32_t mask = candidates(e0, cj, fp, off_s);
+    uint32_t e[BUCKET];
+    for (int j = 0;; j++) {
+        while (mask) {
+            const int i = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            const uint32_t x = (j == 0) ? pick(e0, i) : pick(e, i);
+            if (target_of(p, base + (x & OFFMASK)) == key)
+                return true;
+        }
+        if (cj <= (uint32_t)BUCKET || j + 1 >= SPILL)
+            return false;
+        // The bucket overflowed: follow the spill chain (rare, dependent).
+        bj = (bj + 1 == p.nb) ? 0u : bj + 1;
+        cj = (uint32_t)ld(&p.hdr[(uint64_t)par * p.nb + bj]);
+        load_bucket(rs, bj, e);
+        mask = candidates(e, cj, fp, off_s);
     }
 }
 
@@ -391,12 +433,15 @@ __device__ __forceinline__ void load_bucket(const Params &p, uint32_t par,
 template <int M, int EB>
 __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 {
-    __shared__ uint32_t sh_pay[MAXG];
-    __shared__ uint32_t sh_scan[WAVES];
-    __shared__ uint64_t sh_red[3 * WAVES];
-    __shared__ int sh_bad;
+    __shared__ uint32_t sh_wave[WAVES];
+    __shared__ uint64_t sh_res[4];
 
     const uint32_t G = gridDim.x, w = blockIdx.x, t = threadIdx.x;
+    const uint32_t wave = t >> 6, lane = t & 63;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        p.ent, (short)0, (int)(p.nb * (uint32_t)(BUCKET * 4)), 0x00020000);
+    const uint32_t W = p.bmw * 32u;  // dense window width in keys
+
     uint32_t src[M], tgt[M];
     bool usable[M];
 #pragma unroll
@@ -411,29 +456,57 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
     bool failed = false;
 
     for (;;) {
-        // ---- 1. gather: (active << 16 | free) per workgroup
+        // ---- 1. gather: every workgroup's free slots and active swaps
         uint32_t f = 0, a = 0;
 #pragma unroll
         for (int m = 0; m < M; m++) {
             f += (usable[m] && src[m] == EMPTY) ? 1u : 0u;
             a += (src[m] != EMPTY) ? 1u : 0u;
         }
-        uint32_t Fw, Aw;
-        const uint32_t lane_off = block_excl_scan(f, &Fw, sh_scan);
-        (void)block_excl_scan(a, &Aw, sh_scan);
-        if (!gather(p, ++epoch, (Aw << 16) | Fw, sh_pay, &sh_bad)) {
+        const uint32_t x = (a << 16) | f;  // both sums stay below 2^16
+        const uint32_t xi = wave_incl_scan(x);
+        if (lane == 63)
+            sh_wave[wave] = xi;
+        wait_mem();
+        __syncthreads();
+        uint32_t below = 0, wgtot = 0;
+#pragma unroll
+        for (int i = 0; i < WAVES; i++) {
+            const uint32_t v = sh_wave[i];
+            below += ((uint32_t)i < wave) ? v : 0u;
+            wgtot += v;
+        }
+        const uint32_t lane_off = (below + xi - x) & 0xFFFFu;
+        ++epoch;
+        if (wave == 0) {
+            uint64_t pre = 0, totF = 0, totA = 0;
+            bool ok = true;
+            if (G == 1) {
+                totF = wgtot & 0xFFFFu;
+                totA = wgtot >> 16;
+            } else {
+                ok = gather_wave0(p, epoch, wgtot, [&](uint32_t v, uint32_t y) {
+                    pre += (v < w) ? (y & 0xFFFFu) : 0u;
+                    totF += y & 0xFFFFu;
+                    totA += y >> 16;
+                });
+                pre = wave_sum64(pre);
+                totF = wave_sum64(totF);
+                totA = wave_sum64(totA);
+            }
+            if (lane == 0) {
+                sh_res[0] = pre;
+                sh_res[1] = totF;
+                sh_res[2] = totA;
+                sh_res[3] = ok ? 0u : 1u;
+            }
+        }
+        __syncthreads();
+        const uint64_t pre = sh_res[0], totF = sh_res[1], totA = sh_res[2];
+        if (sh_res[3]) {
             failed = true;
             break;
         }
-        uint64_t pre = 0, totF = 0, totA = 0;
-        for (uint32_t v = t; v < G; v += WG) {
-            const uint32_t x = sh_pay[v];
-            const uint32_t fv = x & 0xFFFFu;
-            pre += (v < w) ? fv : 0u;
-            totF += fv;
-            totA += x >> 16;
-        }
-        block_sum3(pre, totF, totA, sh_red);
         if (cursor == 0 && totA == 0)
             break;
         if (rounds >= p.max_rounds) {
@@ -465,54 +538,79 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             }
         }
 
-        // ---- 3. reserve R[H[s]], mark the dense window, clean the old parity
-        uint32_t act = 0;
+        // ---- 3. reserve H[s], mark the dense window, clean the old parity
+        uint32_t act = 0, pos[M];
 #pragma unroll
         for (int m = 0; m < M; m++) {
+            pos[m] = 0;
             if (src[m] != EMPTY) {
                 act++;
-                const uint32_t b = bucket_of(tgt[m], p.nb);
-                const uint32_t pos = __hip_atomic_fetch_add(
-                    &p.cnt[(uint64_t)par * p.nb + b], 1u, __ATOMIC_RELAXED,
-                    __HIP_MEMORY_SCOPE_AGENT);
-                if (pos < (uint32_t)BUCKET)
-                    st(&p.ent[(uint64_t)b * BUCKET + pos], src[m]);
-                else
-                    __hip_atomic_fetch_max(&p.ovf[(uint64_t)par * p.nb + b],
-                                           src[m] + 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (tgt[m] >= cnew && tgt[m] < cursor) {
-                    const uint32_t d = tgt[m] - cnew;
+                pos[m] = __hip_atomic_fetch_add(
+                    hdr_cnt(&p.hdr[(uint64_t)par * p.nb + bucket_of(tgt[m], p.nb)]), 1u,
+                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t d = tgt[m] - cnew;
+                if (tgt[m] >= cnew && d < W)
                     __hip_atomic_fetch_or(&p.bm[(uint64_t)par * p.bmw + (d >> 5)],
                                           1u << (d & 31u), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (src[m] != EMPTY) {
+                const uint32_t off = src[m] - cnew;
+                const uint32_t b = bucket_of(tgt[m], p.nb);
+                if (off <= OFFMASK)
+                    reserve_finish(p, par, b, pos[m],
+                                   (fingerprint(tgt[m]) << OFFB) | off, src[m]);
+                else
+                    __hip_atomic_fetch_max(hdr_ovf(&p.hdr[(uint64_t)par * p.nb + b]),
+                                           src[m] + 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         {
             const uint32_t op = par ^ 1u;
             for (uint32_t i = w * WG + t; i < p.nb; i += G * WG) {
-                st(&p.cnt[(uint64_t)op * p.nb + i], 0u);
-                st(&p.ovf[(uint64_t)op * p.nb + i], 0u);
+                clear_rmw(hdr_cnt(&p.hdr[(uint64_t)op * p.nb + i]));
+                clear_rmw(hdr_ovf(&p.hdr[(uint64_t)op * p.nb + i]));
             }
             for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
-                st(&p.bm[(uint64_t)op * p.bmw + i], 0u);
+                clear_rmw(&p.bm[(uint64_t)op * p.bmw + i]);
         }
         attempts += act;
 
-        // ---- 4. barrier (carries the active count for the statistics)
-        uint32_t actw;
-        (void)block_excl_scan(act, &actw, sh_scan);
-        if (!gather(p, ++epoch, actw, sh_pay, &sh_bad)) {
+        // ---- 4. barrier (wave 0 of workgroup 0 also totals the attempts)
+        {
+            const uint32_t ai = wave_incl_scan(act);
+            if (lane == 63)
+                sh_wave[wave] = ai;
+        }
+        wait_mem();
+        __syncthreads();
+        ++epoch;
+        if (wave == 0) {
+            uint32_t actw = 0;
+#pragma unroll
+            for (int i = 0; i < WAVES; i++)
+                actw += sh_wave[i];
+            bool ok = true;
+            uint64_t tot = 0;
+            if (G == 1)
+                tot = actw;
+            else
+                ok = gather_wave0(p, epoch, actw,
+                                  [&](uint32_t, uint32_t y) { tot += y; });
+            tot = wave_sum64(tot);
+            if (lane == 0) {
+                sh_res[3] = ok ? 0u : 1u;
+                maxact = max(maxact, tot);
+            }
+        }
+        __syncthreads();
+        if (sh_res[3]) {
             failed = true;
             break;
-        }
-        if (w == 0) {
-            uint64_t tot = 0, d0 = 0, d1 = 0;
-            for (uint32_t v = t; v < G; v += WG)
-                tot += sh_pay[v];
-            block_sum3(tot, d0, d1, sh_red);
-            maxact = max(maxact, tot);
         }
 
         // ---- 5. commit test and swap
@@ -521,29 +619,36 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             if (src[m] == EMPTY)
                 continue;
             const uint32_t s = src[m], h = tgt[m];
-            uint32_t ct, ot, et[BUCKET];
-            load_bucket(p, par, bucket_of(h, p.nb), ct, ot, et);
-            const bool fresh = s < cursor;  // s >= cnew holds for all fresh
-            uint32_t bits = 0, cs = 0, os = 0, es[BUCKET];
-            if (fresh) {
-                bits = ld(&p.bm[(uint64_t)par * p.bmw + ((s - cnew) >> 5)]);
-            } else {
-                load_bucket(p, par, bucket_of(s, p.nb), cs, os, es);
-            }
-            Rec<EB == 0 ? 4 : EB> rs, rh;
+            const uint32_t bt = bucket_of(h, p.nb);
+            const uint64_t ht = ld(&p.hdr[(uint64_t)par * p.nb + bt]);
+            uint32_t et[BUCKET];
+            load_bucket(rs, bt, et);
+            const uint32_t ds = s - cnew;  // s >= cnew for every active swap
+            const bool inwin = ds < W;
+            uint32_t bits = 0;
+            if (inwin)
+                bits = ld(&p.bm[(uint64_t)par * p.bmw + (ds >> 5)]);
+            Rec<EB == 0 ? 4 : EB> r_s, r_h;
             if (EB != 0) {
-                rs.load(p.A, s);
-                rh.load(p.A, h);
+                r_s.load(p.A, s);
+                r_h.load(p.A, h);
             }
-            bool lose = outranked(p, ct, ot, et, s, h);
-            if (fresh)
-                lose = lose || ((bits >> ((s - cnew) & 31u)) & 1u);
-            else
-                lose = lose || outranked(p, cs, os, es, s, s);
+            bool lose = outranked(p, rs, par, cnew, s, h, bt, ht, et);
+            if (inwin) {
+                lose = lose || ((bits >> (ds & 31u)) & 1u);
+            } else if (!lose) {
+                // Source outside the dense window (an old loser): look the
+                // key s up in the table.
+                const uint32_t bs = bucket_of(s, p.nb);
+                const uint64_t hs = ld(&p.hdr[(uint64_t)par * p.nb + bs]);
+                uint32_t es[BUCKET];
+                load_bucket(rs, bs, es);
+                lose = outranked(p, rs, par, cnew, s, s, bs, hs, es);
+            }
             if (!lose) {
                 if (EB != 0) {
-                    rh.store(p.A, s);
-                    rs.store(p.A, h);
+                    r_h.store(p.A, s);
+                    r_s.store(p.A, h);
                 } else {
                     swap_generic(p.A, p.eb, s, h);
                 }
@@ -557,15 +662,17 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
     }
 
     // ---- statistics
-    uint64_t s_att = attempts, s_ret = retries, s_self = selfl;
-    block_sum3(s_att, s_ret, s_self, sh_red);
-    if (t == 0) {
+    uint64_t s_att = wave_sum64(attempts), s_ret = wave_sum64(retries),
+             s_self = wave_sum64(selfl);
+    if (lane == 0) {
         __hip_atomic_fetch_add(&p.dstats[S_ATTEMPTS], s_att, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&p.dstats[S_RETRIES], s_ret, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&p.dstats[S_SELF], s_self, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (t == 0) {
         if (w == 0) {
             st(&p.dstats[S_ROUNDS], rounds);
             st(&p.dstats[S_MAXACT], maxact);
@@ -651,11 +758,11 @@ struct Plan {
 uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *nb_out, uint64_t *bmw_out)
 {
     const uint64_t nb = std::max<uint64_t>(1, (k + LAMBDA - 1) / LAMBDA);
-    const uint64_t bmw = std::max<uint64_t>(1, (k + 31) / 32);
+    const uint64_t bmw = std::max<uint64_t>(1, (2 * k + 31) / 32);
     if (nb_out) *nb_out = nb;
     if (bmw_out) *bmw_out = bmw;
     uint64_t bytes = nb * BUCKET * 4       // entries
-                   + 2 * nb * 4 * 2        // cnt, ovf (two parities)
+                   + 2 * nb * 8            // headers (two parities)
                    + 2 * bmw * 4           // dense window (two parities)
                    + 8;                    // error word (padded)
     if (G > 1)
@@ -928,16 +1035,14 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
     p.bmw = pl.bmw;
     p.dstats = dstats;
     p.max_rounds = n + 64;
-    // Carve the counted words: [ent | cnt | ovf | bm | flags | err]; ent
-    // first so that every bucket is one aligned 64-byte line.
+    // Carve the counted words: [ent | hdr | bm | flags | err]; ent first so
+    // that every bucket is one aligned 128-byte block.
     unsigned char *cur = base;
     if (!pl.single) {
         p.ent = reinterpret_cast<uint32_t *>(cur);
         cur += (uint64_t)pl.nb * BUCKET * 4;
-        p.cnt = reinterpret_cast<uint32_t *>(cur);
-        cur += 2ull * pl.nb * 4;
-        p.ovf = reinterpret_cast<uint32_t *>(cur);
-        cur += 2ull * pl.nb * 4;
+        p.hdr = reinterpret_cast<uint64_t *>(cur);
+        cur += 2ull * pl.nb * 8;
         p.bm = reinterpret_cast<uint32_t *>(cur);
         cur += 2ull * pl.bmw * 4;
         if (pl.G > 1) {
