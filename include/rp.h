@@ -14,7 +14,8 @@
  * n^(1-eps), Theorem on relaxed-PIP random permutation via the Decomposable
  * Property of Section 4) implemented in the RP-Final form of Section 7.4 and
  * Appendix A.2 (single reservation on R[H[i]], dense array for the keys of
- * the swaps added in the current round, hash table for the rest).  Auxiliary
+ * the swaps added in the current round; the reservation array R itself is
+ * hashed into O(k) priority slots written with atomic max).  Auxiliary
  * space is O(n^(1-eps)) words: every byte of device memory a call allocates
  * is counted and the total never exceeds 8 * floor(n^(1-eps)) bytes.
  *
@@ -60,7 +61,8 @@ extern "C" {
  *   retries           attempts that lost and were carried to the next round
  *   max_active        largest number of swaps attempted in one round
  *   self_loops        swaps with H[i] = i, retired without a reservation
- *   grid, slots_per_lane, buckets   launch shape and table size used
+ *   grid, slots_per_lane, table_slots   launch shape and number of 32-bit
+ *                     slots of the hashed reservation array
  *   status            RP_OK, or RP_ETIMEOUT if the device watchdog fired
  */
 typedef struct rp_stats {
@@ -74,7 +76,7 @@ typedef struct rp_stats {
     uint64_t self_loops;
     uint64_t grid;
     uint64_t slots_per_lane;
-    uint64_t buckets;
+    uint64_t table_slots;
     int64_t status;
 } rp_stats;
 
@@ -89,7 +91,7 @@ uint64_t rp_aux_bound_words(uint64_t n, double eps);
 /*
  * Plan a call without running it (host only, no GPU): fills *stats_out
  * (host) with the k, aux_words, aux_bound_words, grid, slots_per_lane and
- * buckets that rp_shuffle_inplace would use on device `device` for these
+ * table_slots that rp_shuffle_inplace would use on device `device` for these
  * arguments; the other fields are zero.  Returns RP_OK, RP_EINVAL or
  * RP_ENOMEM (bound too small for even one active swap).  device < 0 assumes
  * an MI355X with 256 compute units.

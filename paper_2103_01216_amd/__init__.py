@@ -30,7 +30,7 @@ _ERRORS = {RP_EINVAL: "RP_EINVAL", RP_ENOMEM: "RP_ENOMEM",
 
 STATS_FIELDS = ("k", "aux_words", "aux_bound_words", "rounds", "attempts",
                 "retries", "max_active", "self_loops", "grid",
-                "slots_per_lane", "buckets", "status")
+                "slots_per_lane", "table_slots", "status")
 
 
 class rp_stats(ctypes.Structure):

@@ -13,49 +13,60 @@
 // One persistent cooperative kernel runs every round.  Each lane owns up to M
 // swap slots held in registers (the active list); a slot is either empty or
 // holds an unfinished swap (s, H[s]).  A round is
-//   1. gather   all workgroups exchange (free slots, active swaps) through a
-//               flag all-gather; from it every workgroup derives the same new
-//               cursor and its own contiguous share of the fresh indices, so
-//               the active set is always the top unfinished swaps in the
-//               sequential order (decreasing index), as the paper requires;
+//   1. gather   all workgroups exchange (free slots, active swaps, oldest
+//               active source) through a flag all-gather; from it every
+//               workgroup derives the same new cursor and its own contiguous
+//               share of the fresh indices, so the active set is always the
+//               top unfinished swaps in the sequential order (decreasing
+//               index), as the paper requires;
 //   2. refill   free slots take fresh indices (decreasing), H[s] is computed
 //               (seed mode) or read; self-loops retire at once (Section 4.1
-//               removes them; a swap with H[s] = s is a no-op);
-//   3. reserve  each active swap adds an entry for key H[s] to the slot
-//               table, and sets bit H[s] of the dense window when H[s] lies
-//               in it;
+//               removes them; a swap with H[s] = s is a no-op); both records
+//               of every active swap are read;
+//   3. reserve  the priority write of Algorithm 1 on R[H[s]], into a hashed
+//               reservation array: R[x] is replaced by two slots
+//               R'[h1(x)], R'[h2(x)] of an O(k)-word array, each updated with
+//               an atomic max of the swap's priority; bit H[s] of the dense
+//               window is set when H[s] lies in it;
 //   4. barrier
-//   5. commit   swap s wins iff no active swap with a larger source (earlier
-//               in the sequential order) targets H[s] (table lookup) and no
-//               active swap targets s (dense window bit; table lookup for the
+//   5. commit   swap s wins iff it is still the maximum in one of its two
+//               slots (so no active swap with a larger source, i.e. earlier
+//               in the sequential order, targets H[s]) and no active swap
+//               targets s (dense window bit; the two slots of key s for the
 //               rare source outside the window) -- the single-reservation
-//               test of Appendix A.2, with the priority write resolved at
-//               read time.  Winners swap A[s] and A[H[s]]; losers stay in
-//               their slots for the next round (the paper's pack step becomes
-//               the per-workgroup prefix sum over free slots in step 1).
-// The table headers and the dense window are double-buffered by round parity
-// and the stale parity is cleared during step 3: the cleaning phase of
-// Appendix A.1.
+//               test of Appendix A.2.  Winners swap A[s] and A[H[s]]; losers
+//               stay in their slots for the next round (the paper's pack step
+//               becomes the per-workgroup prefix sum over free slots in
+//               step 1).
+//
+// Why the hashed array is exact: a slot holds the maximum priority over all
+// keys that hash to it, so "s is the maximum in a slot of key x" implies that
+// no active swap with higher priority reserved x (it would have raised both
+// of x's slots).  Collisions between different keys can only make a swap lose
+// a round it could have won (it retries next round; the top unfinished swap
+// is the maximum everywhere and always commits), never win wrongly.
+//
+// Priorities are (tag:8 | rank:24) with rank = s - cursor_new and tag = round
+// number mod 256, so values written in later rounds are larger and the array
+// needs no cleaning between rounds; every 256 rounds all slots are reset
+// behind an extra barrier.  The refill is throttled so that ranks stay below
+// 2^24.  The dense window is double-buffered by round parity and the stale
+// parity is cleared during step 3: the cleaning phase of Appendix A.1.
 //
 // Auxiliary layout (device memory, every byte counted against the bound):
-//   ent[b * 32 + j]     bucket b: 32 entries of 32 bits (one 128-byte block);
-//                       entry = fingerprint(key):6 | (source - base):26
-//   hdr[par * nb + b]   64 bits: low = reservations that tried bucket b this
-//                       round, high = 1 + largest source whose reservation
-//                       could not be placed (0 = none)
+//   slots[T]            hashed reservation array, 32-bit priorities
 //   bm[par * bmw + i]   dense window: bit x set iff an active swap targets
-//                       base + x, for x < 32 * bmw (at least 2k)
-//   flags[par * G + w]  gather flags: epoch:32 | payload:32
+//                       cursor_new + x, for x < 32 * bmw (at least 2k)
+//   flags[par * G + w]  gather flags: epoch:16 | payload:48
 //   err                 watchdog / error word
 // RP-Final keeps R for the round's consecutive keys in a prefix-sized array;
 // here that array holds one bit per key, because the commit test only asks
 // whether any other active swap targets the source.
 //
-// Cross-workgroup data is accessed only with device-coherent operations:
-// relaxed agent-scope atomics, and 16-byte buffer loads with the device-scope
-// cache policy for table blocks.  A workgroup waits for all of its memory
-// operations to complete before it publishes its barrier flag, and every
-// access after a barrier is issued after the flags were observed.
+// Cross-workgroup data is accessed only with device-coherent relaxed
+// agent-scope atomics.  A workgroup waits for all of its memory operations to
+// complete before it publishes its barrier flag, and every access after a
+// barrier is issued after the flags were observed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,15 +83,13 @@ namespace {
 
 constexpr int WG = 256;                 // threads per workgroup
 constexpr int WAVES = WG / 64;
-constexpr int BUCKET = 32;              // entries per bucket (128 bytes)
-constexpr int LAMBDA = 14;              // target reservations per bucket
-constexpr int SPILL = 4;                // buckets a reservation may try
-constexpr uint32_t OFFB = 26;           // entry = fingerprint:6 | offset:26
-constexpr uint32_t OFFMASK = (1u << OFFB) - 1u;
+constexpr uint32_t RANKB = 24;          // priority = tag:8 | rank:24
+constexpr uint32_t RANKMAX = (1u << RANKB) - 1u;
+constexpr uint32_t TAG_CYCLE = 256;     // rounds between full resets
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int MAXG = 2048;              // largest grid the gather supports
 constexpr uint64_t WATCHDOG_TICKS = 500000000ull;  // 5 s at 100 MHz
-constexpr int SC1 = 16;                 // cache policy: device scope
+constexpr double TABLE_RATIO = 1.0;     // reservation slots per active swap
 
 struct Params {
     unsigned char *A;
@@ -89,10 +98,11 @@ struct Params {
     uint32_t n;
     uint32_t eb;
     uint32_t k;
-    uint32_t nb;         // buckets
+    uint32_t T;          // reservation slots
     uint32_t bmw;        // dense-window words per parity
-    uint32_t *ent;
-    uint64_t *hdr;
+    uint32_t choices;    // reservation slots per key: 1 or 2
+    uint32_t hoist;      // 1: read records before the barrier
+    uint32_t *slots;
     uint32_t *bm;
     uint64_t *flags;
     uint32_t *err;
@@ -102,7 +112,7 @@ struct Params {
 
 // rp_stats word indices
 enum { S_K, S_AUX, S_BOUND, S_ROUNDS, S_ATTEMPTS, S_RETRIES, S_MAXACT,
-       S_SELF, S_GRID, S_SLOTS, S_BUCKETS, S_STATUS, S_WORDS };
+       S_SELF, S_GRID, S_SLOTS, S_TABLE, S_STATUS, S_WORDS };
 
 // ---------------------------------------------------------------- memory ops
 
@@ -133,8 +143,6 @@ __device__ __forceinline__ void wait_mem()
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-__device__ __forceinline__ uint32_t *hdr_cnt(uint64_t *h) { return reinterpret_cast<uint32_t *>(h); }
-__device__ __forceinline__ uint32_t *hdr_ovf(uint64_t *h) { return reinterpret_cast<uint32_t *>(h) + 1; }
 
 // ------------------------------------------------------- exact integer math
 
@@ -183,15 +191,18 @@ __device__ __forceinline__ uint32_t target_of(const Params &p, uint32_t s)
     return p.H ? (uint32_t)p.H[s] : seed_target(p.seed, s);
 }
 
-__device__ __forceinline__ uint32_t bucket_of(uint32_t key, uint32_t nb)
+// The two reservation slots of key x: multiplicative hashing with two odd
+// 64-bit constants, scaled to [0, T).
+__device__ __forceinline__ uint32_t slot1(uint32_t key, uint32_t T)
 {
     const uint32_t h = (uint32_t)(((uint64_t)key * 0x9E3779B97F4A7C15ull) >> 32);
-    return (uint32_t)(((uint64_t)h * nb) >> 32);
+    return (uint32_t)(((uint64_t)h * T) >> 32);
 }
 
-__device__ __forceinline__ uint32_t fingerprint(uint32_t key)
+__device__ __forceinline__ uint32_t slot2(uint32_t key, uint32_t T)
 {
-    return (uint32_t)(((uint64_t)key * 0xD6E8FEB86659FD93ull) >> 58);
+    const uint32_t h = (uint32_t)(((uint64_t)key * 0xC2B2AE3D27D4EB4Full) >> 32);
+    return (uint32_t)(((uint64_t)h * T) >> 32);
 }
 
 // ----------------------------------------------------------- wave helpers
@@ -218,38 +229,54 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 
 // --------------------------------------------------------------- the gather
 
-// Wave 0 of every workgroup: publish `payload` under `epoch`, wait for every
-// workgroup's flag of the same epoch and return, per lane, the payloads of
-// workgroups lane, lane+64, ... through `visit`.  Flags are double-buffered
-// by epoch parity: a workgroup cannot publish epoch e+2 before every
-// workgroup has read epoch e.  Returns false when the watchdog fired.
-// The caller has made this workgroup's memory operations complete (wait_mem
-// in every wave, then a workgroup barrier) before calling.
+// Wave 0 of every workgroup: publish the 48-bit `payload` under `epoch`,
+// wait for every workgroup's flag of the same epoch and hand each payload to
+// `visit` (lane-strided).  Flags hold epoch:16 | payload:48 and are
+// double-buffered by epoch parity: a workgroup cannot publish epoch e+2
+// before every workgroup has read epoch e, so 16 epoch bits never alias.
+// Returns false when the watchdog fired.  The caller has made this
+// workgroup's memory operations complete (wait_mem in every wave, then a
+// workgroup barrier) before calling.
 template <typename Visit>
 __device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t epoch,
-                                             uint32_t payload, Visit visit)
+                                             uint64_t payload, Visit visit)
 {
     const uint32_t G = gridDim.x, lane = threadIdx.x & 63;
+    const uint32_t e16 = epoch & 0xFFFFu;
     uint64_t *fl = p.flags + (uint64_t)(epoch & 1u) * G;
     if (lane == 0)
-        st(&fl[blockIdx.x], ((uint64_t)epoch << 32) | payload);
+        st(&fl[blockIdx.x], ((uint64_t)e16 << 48) | payload);
+    // Poll every flag this lane covers at once; look at the clock and the
+    // error word only every 64 sweeps so that a sweep costs one load latency.
+    const int nj = (int)((G + 63u) / 64u);
+    uint32_t pending = 0;
+#pragma unroll 1
+    for (int j = 0; j < nj; j++)
+        pending |= (lane + 64u * j < G) ? (1u << j) : 0u;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     bool ok = true;
-    for (uint32_t v = lane; v < G; v += 64) {
-        uint64_t f = ld(&fl[v]);
-        while ((uint32_t)(f >> 32) != epoch) {
+    for (uint32_t sweep = 1; pending; sweep++) {
+#pragma unroll 1
+        for (int j = 0; j < nj; j++) {
+            if (!(pending & (1u << j)))
+                continue;
+            const uint32_t v = lane + 64u * j;
+            const uint64_t f = ld(&fl[v]);
+            if ((uint32_t)(f >> 48) == e16) {
+                pending &= ~(1u << j);
+                visit(v, f & ((1ull << 48) - 1));
+            }
+        }
+        if (pending && (sweep & 63u) == 0) {
             if (__builtin_amdgcn_s_memrealtime() - t0 > WATCHDOG_TICKS ||
                 ld(p.err) != 0u) {
                 st(p.err, 1u);
                 ok = false;
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
-            f = ld(&fl[v]);
         }
-        if (!ok)
-            break;
-        visit(v, (uint32_t)f);
+        if (pending)
+            __builtin_amdgcn_s_sleep(1);
     }
     asm volatile("" ::: "memory");
     return __all(ok);
@@ -317,116 +344,32 @@ __device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
     }
 }
 
-// ------------------------------------------------------------- slot table
-//
-// A reservation of swap s on key x is one 32-bit entry in bucket
-// bucket_of(x): the 6-bit fingerprint of x and s - base, where base is the
-// round's lowest possible active source (the new cursor).  It goes into the
-// first of buckets b, b+1, ..., b+SPILL-1 (mod nb) whose counter (one atomic
-// add) shows a free entry.  A bucket's counter counts every attempt on it,
-// so "count <= BUCKET" proves that no reservation moved on from it.  A
-// reservation that finds SPILL full buckets, or whose offset does not fit in
-// 26 bits, raises the overflow word of its home bucket to s + 1 instead,
-// which makes every swap with a smaller source on that bucket lose (safe;
-// the sizes keep it vanishingly rare).  The key of an entry is recomputed
-// only when its fingerprint matches.
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void load_bucket(__amdgpu_buffer_rsrc_t rs, uint32_t b,
-                                            uint32_t *e)
-{
-#pragma unroll
-    for (int i = 0; i < BUCKET / 4; i++) {
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
-            rs, (int)(b * (uint32_t)(BUCKET * 4) + i * 16), 0, SC1);
-        e[4 * i] = v.x;
-        e[4 * i + 1] = v.y;
-        e[4 * i + 2] = v.z;
-        e[4 * i + 3] = v.w;
-    }
-}
-
-// Bit mask of entries j < min(c, BUCKET) with fingerprint fp whose source
-// outranks (is larger than) base + off_s.
-__device__ __forceinline__ uint32_t candidates(const uint32_t *e, uint32_t c,
-                                               uint32_t fp, uint32_t off_s)
-{
-    const uint32_t m = min(c, (uint32_t)BUCKET);
-    uint32_t mask = 0;
-#pragma unroll
-    for (int j = 0; j < BUCKET; j++) {
-        const uint32_t x = e[j];
-        const bool hit = (uint32_t)j < m && (x >> OFFB) == fp && (x & OFFMASK) > off_s;
-        mask |= hit ? (1u << j) : 0u;
-    }
-    return mask;
-}
-
-// e[i] for a run-time i without dynamic register indexing (which would move
-// the array to scratch memory).
-__device__ __forceinline__ uint32_t pick(const uint32_t *e, int i)
-{
-    uint32_t x = 0;
-#pragma unroll
-    for (int j = 0; j < BUCKET; j++)
-        x = (j == i) ? e[j] : x;
-    return x;
-}
-
-__device__ __forceinline__ void reserve_finish(const Params &p, uint32_t par,
-                                               uint32_t b, uint32_t pos,
-                                               uint32_t e, uint32_t s)
-{
-    uint32_t bj = b;
-    for (int j = 0;; j++) {
-        if (pos < (uint32_t)BUCKET) {
-            st(&p.ent[(uint64_t)bj * BUCKET + pos], e);
-            return;
-        }
-        if (j + 1 >= SPILL)
-            break;
-        bj = (bj + 1 == p.nb) ? 0u : bj + 1;
-        pos = __hip_atomic_fetch_add(hdr_cnt(&p.hdr[(uint64_t)par * p.nb + bj]), 1u,
-                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __hip_atomic_fetch_max(hdr_ovf(&p.hdr[(uint64_t)par * p.nb + b]), s + 1u,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// True iff some active swap with a source larger than s reserved `key` this
-// round (exact), or an overflow on the home bucket forbids s (conservative).
-// h0 and e0 are the home bucket's header and entries, already loaded.
-__device__ __forceinline__ bool outranked(const Params &p, __amdgpu_buffer_rsrc_t rs,
-                                          uint32_t par, uint32_t base, uint32_t s,
-                                          uint32_t key, uint32_t b, uint64_t h0,
-                                          const uint32_t *e0)
-{
-    if ((uint32_t)(h0 >> 32) > s + 1u)
-        return true;
-    const uint32_t fp = fingerprint(key), off_s = s - base;
-    uint32_t cj = (uint32_t)h0, bj = b;
-    uint32_t mask = candidates(e0, cj, fp, off_s);
-    uint32_t e[BUCKET];
-    for (int j = 0;; j++) {
-        while (mask) {
-            const int i = __builtin_ctz(mask);
-            mask &= mask - 1u;
-            const uint32_t x = (j == 0) ? pick(e0, i) : pick(e, i);
-            if (target_of(p, base + (x & OFFMASK)) == key)
-                return true;
-        }
-        if (cj <= (uint32_t)BUCKET || j + 1 >= SPILL)
-            return false;
-        // The bucket overflowed: follow the spill chain (rare, dependent).
-        bj = (bj + 1 == p.nb) ? 0u : bj + 1;
-        cj = (uint32_t)ld(&p.hdr[(uint64_t)par * p.nb + bj]);
-        load_bucket(rs, bj, e);
-        mask = candidates(e, cj, fp, off_s);
-    }
-}
-
 // -------------------------------------------------------------- the kernel
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+    return v;
+}
+
+// Barrier with no payload (the periodic reset of the reservation array).
+__device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t epoch,
+                                              uint64_t *sh_res)
+{
+    wait_mem();
+    __syncthreads();
+    if ((threadIdx.x >> 6) == 0) {
+        bool ok = true;
+        if (gridDim.x > 1)
+            ok = gather_wave0(p, epoch, 0, [](uint32_t, uint64_t) {});
+        if ((threadIdx.x & 63) == 0)
+            sh_res[3] = ok ? 0u : 1u;
+    }
+    __syncthreads();
+    return sh_res[3] == 0;
+}
 
 // M: swap slots per lane.  EB: record size held in registers (4, 8, 16), or
 // 0 for any multiple of 4 up to 256 bytes, moved after the decision.
@@ -434,12 +377,11 @@ template <int M, int EB>
 __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 {
     __shared__ uint32_t sh_wave[WAVES];
-    __shared__ uint64_t sh_res[4];
+    __shared__ uint32_t sh_age[WAVES];
+    __shared__ uint64_t sh_res[5];
 
     const uint32_t G = gridDim.x, w = blockIdx.x, t = threadIdx.x;
     const uint32_t wave = t >> 6, lane = t & 63;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        p.ent, (short)0, (int)(p.nb * (uint32_t)(BUCKET * 4)), 0x00020000);
     const uint32_t W = p.bmw * 32u;  // dense window width in keys
 
     uint32_t src[M], tgt[M];
@@ -456,53 +398,69 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
     bool failed = false;
 
     for (;;) {
-        // ---- 1. gather: every workgroup's free slots and active swaps
-        uint32_t f = 0, a = 0;
+        // ---- 1. gather: free slots, active swaps, oldest active source
+        uint32_t f = 0, a = 0, age = 0;
 #pragma unroll
         for (int m = 0; m < M; m++) {
             f += (usable[m] && src[m] == EMPTY) ? 1u : 0u;
-            a += (src[m] != EMPTY) ? 1u : 0u;
+            if (src[m] != EMPTY) {
+                a++;
+                age = max(age, min(src[m] - cursor, RANKMAX));  // losers: src >= cursor
+            }
         }
-        const uint32_t x = (a << 16) | f;  // both sums stay below 2^16
+        const uint32_t x = (a << 16) | f;  // both sums stay below 2^12
         const uint32_t xi = wave_incl_scan(x);
+        const uint32_t agew = wave_max(age);
         if (lane == 63)
             sh_wave[wave] = xi;
+        if (lane == 0)
+            sh_age[wave] = agew;
         wait_mem();
         __syncthreads();
-        uint32_t below = 0, wgtot = 0;
+        uint32_t below = 0, wgtot = 0, wgage = 0;
 #pragma unroll
         for (int i = 0; i < WAVES; i++) {
             const uint32_t v = sh_wave[i];
             below += ((uint32_t)i < wave) ? v : 0u;
             wgtot += v;
+            wgage = max(wgage, sh_age[i]);
         }
         const uint32_t lane_off = (below + xi - x) & 0xFFFFu;
         ++epoch;
         if (wave == 0) {
             uint64_t pre = 0, totF = 0, totA = 0;
+            uint32_t agemax = 0;
             bool ok = true;
             if (G == 1) {
                 totF = wgtot & 0xFFFFu;
                 totA = wgtot >> 16;
+                agemax = wgage;
             } else {
-                ok = gather_wave0(p, epoch, wgtot, [&](uint32_t v, uint32_t y) {
-                    pre += (v < w) ? (y & 0xFFFFu) : 0u;
-                    totF += y & 0xFFFFu;
-                    totA += y >> 16;
+                const uint64_t pay = ((uint64_t)(wgtot >> 16) << 36) |
+                                     ((uint64_t)(wgtot & 0xFFFFu) << 24) | wgage;
+                ok = gather_wave0(p, epoch, pay, [&](uint32_t v, uint64_t y) {
+                    const uint32_t fv = (uint32_t)(y >> 24) & 0xFFFu;
+                    pre += (v < w) ? fv : 0u;
+                    totF += fv;
+                    totA += (uint32_t)(y >> 36) & 0xFFFu;
+                    agemax = max(agemax, (uint32_t)y & RANKMAX);
                 });
                 pre = wave_sum64(pre);
                 totF = wave_sum64(totF);
                 totA = wave_sum64(totA);
+                agemax = wave_max(agemax);
             }
             if (lane == 0) {
                 sh_res[0] = pre;
                 sh_res[1] = totF;
                 sh_res[2] = totA;
                 sh_res[3] = ok ? 0u : 1u;
+                sh_res[4] = agemax;
             }
         }
         __syncthreads();
         const uint64_t pre = sh_res[0], totF = sh_res[1], totA = sh_res[2];
+        const uint32_t agemax = (uint32_t)sh_res[4];
         if (sh_res[3]) {
             failed = true;
             break;
@@ -515,9 +473,23 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             failed = true;
             break;
         }
-        const uint32_t take = (uint32_t)min<uint64_t>(totF, cursor);
+        // Fresh swaps, throttled so that every active rank fits in 24 bits.
+        const uint32_t take = (uint32_t)min<uint64_t>(
+            min<uint64_t>(totF, cursor), (uint64_t)(RANKMAX - agemax));
         const uint32_t cnew = cursor - take;
         const uint32_t par = (uint32_t)(rounds & 1);
+        const uint32_t tag = (uint32_t)(rounds % TAG_CYCLE);
+
+        // Every TAG_CYCLE rounds: reset the reservation array behind an
+        // extra barrier, so that tags restart from 0 over an empty array.
+        if (tag == 0 && rounds > 0) {
+            for (uint32_t i = w * WG + t; i < p.T; i += G * WG)
+                clear_rmw(&p.slots[i]);
+            if (!plain_barrier(p, ++epoch, sh_res)) {
+                failed = true;
+                break;
+            }
+        }
 
         // ---- 2. refill free slots with fresh indices, decreasing
         uint32_t j = (uint32_t)pre + lane_off;
@@ -537,17 +509,33 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                 }
             }
         }
+        // Read both records of every active swap now.  If the swap wins this
+        // round, no other winner touches either location, and every earlier
+        // round's writes completed before the gather above, so these values
+        // are exactly the ones the swap exchanges.
+        Rec<EB == 0 ? 4 : EB> r_s[M], r_h[M];
+        if (EB != 0 && p.hoist) {
+#pragma unroll
+            for (int m = 0; m < M; m++)
+                if (src[m] != EMPTY) {
+                    r_s[m].load(p.A, src[m]);
+                    r_h[m].load(p.A, tgt[m]);
+                }
+        }
 
-        // ---- 3. reserve H[s], mark the dense window, clean the old parity
-        uint32_t act = 0, pos[M];
+        // ---- 3. reserve: priority write on the two slots of H[s]; dense
+        // window bit; clean the stale window parity
+        uint32_t act = 0;
 #pragma unroll
         for (int m = 0; m < M; m++) {
-            pos[m] = 0;
             if (src[m] != EMPTY) {
                 act++;
-                pos[m] = __hip_atomic_fetch_add(
-                    hdr_cnt(&p.hdr[(uint64_t)par * p.nb + bucket_of(tgt[m], p.nb)]), 1u,
-                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t v = (tag << RANKB) | (src[m] - cnew);
+                __hip_atomic_fetch_max(&p.slots[slot1(tgt[m], p.T)], v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (p.choices > 1)
+                    __hip_atomic_fetch_max(&p.slots[slot2(tgt[m], p.T)], v,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t d = tgt[m] - cnew;
                 if (tgt[m] >= cnew && d < W)
                     __hip_atomic_fetch_or(&p.bm[(uint64_t)par * p.bmw + (d >> 5)],
@@ -555,26 +543,8 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-#pragma unroll
-        for (int m = 0; m < M; m++) {
-            if (src[m] != EMPTY) {
-                const uint32_t off = src[m] - cnew;
-                const uint32_t b = bucket_of(tgt[m], p.nb);
-                if (off <= OFFMASK)
-                    reserve_finish(p, par, b, pos[m],
-                                   (fingerprint(tgt[m]) << OFFB) | off, src[m]);
-                else
-                    __hip_atomic_fetch_max(hdr_ovf(&p.hdr[(uint64_t)par * p.nb + b]),
-                                           src[m] + 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
         {
             const uint32_t op = par ^ 1u;
-            for (uint32_t i = w * WG + t; i < p.nb; i += G * WG) {
-                clear_rmw(hdr_cnt(&p.hdr[(uint64_t)op * p.nb + i]));
-                clear_rmw(hdr_ovf(&p.hdr[(uint64_t)op * p.nb + i]));
-            }
             for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
                 clear_rmw(&p.bm[(uint64_t)op * p.bmw + i]);
         }
@@ -600,7 +570,7 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                 tot = actw;
             else
                 ok = gather_wave0(p, epoch, actw,
-                                  [&](uint32_t, uint32_t y) { tot += y; });
+                                  [&](uint32_t, uint64_t y) { tot += y; });
             tot = wave_sum64(tot);
             if (lane == 0) {
                 sh_res[3] = ok ? 0u : 1u;
@@ -613,42 +583,47 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             break;
         }
 
-        // ---- 5. commit test and swap
+        // ---- 5. commit test and swap: issue every load, then decide
+        uint32_t t1[M], t2[M], q1[M], q2[M];
 #pragma unroll
         for (int m = 0; m < M; m++) {
             if (src[m] == EMPTY)
                 continue;
             const uint32_t s = src[m], h = tgt[m];
-            const uint32_t bt = bucket_of(h, p.nb);
-            const uint64_t ht = ld(&p.hdr[(uint64_t)par * p.nb + bt]);
-            uint32_t et[BUCKET];
-            load_bucket(rs, bt, et);
+            t1[m] = ld(&p.slots[slot1(h, p.T)]);
+            t2[m] = (p.choices > 1) ? ld(&p.slots[slot2(h, p.T)]) : 0u;
             const uint32_t ds = s - cnew;  // s >= cnew for every active swap
-            const bool inwin = ds < W;
-            uint32_t bits = 0;
-            if (inwin)
-                bits = ld(&p.bm[(uint64_t)par * p.bmw + (ds >> 5)]);
-            Rec<EB == 0 ? 4 : EB> r_s, r_h;
-            if (EB != 0) {
-                r_s.load(p.A, s);
-                r_h.load(p.A, h);
+            if (EB != 0 && !p.hoist) {
+                r_s[m].load(p.A, s);
+                r_h[m].load(p.A, h);
             }
-            bool lose = outranked(p, rs, par, cnew, s, h, bt, ht, et);
-            if (inwin) {
-                lose = lose || ((bits >> (ds & 31u)) & 1u);
-            } else if (!lose) {
-                // Source outside the dense window (an old loser): look the
-                // key s up in the table.
-                const uint32_t bs = bucket_of(s, p.nb);
-                const uint64_t hs = ld(&p.hdr[(uint64_t)par * p.nb + bs]);
-                uint32_t es[BUCKET];
-                load_bucket(rs, bs, es);
-                lose = outranked(p, rs, par, cnew, s, s, bs, hs, es);
+            if (ds < W) {
+                q1[m] = ld(&p.bm[(uint64_t)par * p.bmw + (ds >> 5)]);
+            } else {
+                q1[m] = ld(&p.slots[slot1(s, p.T)]);
+                q2[m] = (p.choices > 1) ? ld(&p.slots[slot2(s, p.T)]) : 0u;
             }
-            if (!lose) {
+        }
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (src[m] == EMPTY)
+                continue;
+            const uint32_t s = src[m], h = tgt[m];
+            const uint32_t ds = s - cnew;
+            const uint32_t v = (tag << RANKB) | ds;
+            // Target: still the maximum in one of the two slots of H[s].
+            const bool two = p.choices > 1;
+            bool win = (t1[m] == v) || (two && t2[m] == v);
+            // Source: no active swap targets s.  Such a swap has a larger
+            // source, so it would have raised both slots of key s above v.
+            if (ds < W)
+                win = win && !((q1[m] >> (ds & 31u)) & 1u);
+            else
+                win = win && (q1[m] <= v || (two && q2[m] <= v));
+            if (win) {
                 if (EB != 0) {
-                    r_h.store(p.A, s);
-                    r_s.store(p.A, h);
+                    r_h[m].store(p.A, s);
+                    r_s[m].store(p.A, h);
                 } else {
                     swap_generic(p.A, p.eb, s, h);
                 }
@@ -722,7 +697,7 @@ __global__ void rp_init_kernel(uint32_t *aux, uint64_t words32, uint64_t *dstats
         dstats[S_SELF] = 0;
         dstats[S_GRID] = host.grid;
         dstats[S_SLOTS] = host.slots_per_lane;
-        dstats[S_BUCKETS] = host.buckets;
+        dstats[S_TABLE] = host.table_slots;
         dstats[S_STATUS] = 0;
     }
 }
@@ -750,23 +725,30 @@ __global__ void rp_seed_targets_kernel(const uint64_t *idx, uint64_t count,
 
 struct Plan {
     bool single;      // k = 1 path
-    uint32_t G, M, k, nb, bmw;
+    uint32_t G, M, k, T, bmw;
     uint64_t bound, aux_bytes;
     int eb_class;     // 4, 8, 16 or 0
 };
 
-uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *nb_out, uint64_t *bmw_out)
+double table_ratio()
 {
-    const uint64_t nb = std::max<uint64_t>(1, (k + LAMBDA - 1) / LAMBDA);
+    const char *v = getenv("RP_TABLE_RATIO");
+    const double r = (v && *v) ? atof(v) : TABLE_RATIO;
+    return (r > 0.05 && r < 64.0) ? r : TABLE_RATIO;
+}
+
+// Device bytes the rounds path allocates for k active swaps on G workgroups.
+uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_out)
+{
+    const uint64_t T = std::max<uint64_t>(2, (uint64_t)std::ceil(table_ratio() * (double)k));
     const uint64_t bmw = std::max<uint64_t>(1, (2 * k + 31) / 32);
-    if (nb_out) *nb_out = nb;
+    if (T_out) *T_out = T;
     if (bmw_out) *bmw_out = bmw;
-    uint64_t bytes = nb * BUCKET * 4       // entries
-                   + 2 * nb * 8            // headers (two parities)
-                   + 2 * bmw * 4           // dense window (two parities)
-                   + 8;                    // error word (padded)
+    uint64_t bytes = ((T * 4 + 7) / 8) * 8     // reservation array (padded)
+                   + 2 * bmw * 4               // dense window (two parities)
+                   + 8;                        // error word (padded)
     if (G > 1)
-        bytes += 2 * G * 8;                // gather flags (two parities)
+        bytes += 2 * G * 8;                    // gather flags (two parities)
     return bytes;
 }
 
@@ -783,7 +765,7 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
     pl->bound = rp_aux_bound_words(n, eps);
     pl->eb_class = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
     const uint64_t budget = pl->bound * 8;
-    // The persistent path needs at least one bucket and k >= 2.
+    // The persistent path needs k >= 2.
     if (aux_bytes_for(2, 1, nullptr, nullptr) > budget) {
         pl->single = true;
         pl->k = 1;
@@ -831,12 +813,12 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
         pl->aux_bytes = 8;
         return RP_OK;
     }
-    uint64_t nb, bmw;
-    pl->aux_bytes = aux_bytes_for(k, G, &nb, &bmw);
+    uint64_t T, bmw;
+    pl->aux_bytes = aux_bytes_for(k, G, &T, &bmw);
     pl->k = (uint32_t)k;
     pl->G = (uint32_t)G;
     pl->M = (uint32_t)M;
-    pl->nb = (uint32_t)nb;
+    pl->T = (uint32_t)T;
     pl->bmw = (uint32_t)bmw;
     return RP_OK;
 }
@@ -923,7 +905,7 @@ void fill_host_stats(const Plan &pl, rp_stats *s)
     s->aux_bound_words = pl.bound;
     s->grid = pl.G;
     s->slots_per_lane = pl.M;
-    s->buckets = pl.nb;
+    s->table_slots = pl.T;
 }
 
 }  // namespace
@@ -1031,18 +1013,17 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
     p.n = (uint32_t)n;
     p.eb = elem_bytes;
     p.k = pl.k;
-    p.nb = pl.nb;
+    p.T = pl.T;
+    p.choices = (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)));
+    p.hoist = env_int("RP_HOIST", 1) ? 1u : 0u;
     p.bmw = pl.bmw;
     p.dstats = dstats;
     p.max_rounds = n + 64;
-    // Carve the counted words: [ent | hdr | bm | flags | err]; ent first so
-    // that every bucket is one aligned 128-byte block.
+    // Carve the counted words: [slots | bm | flags | err].
     unsigned char *cur = base;
     if (!pl.single) {
-        p.ent = reinterpret_cast<uint32_t *>(cur);
-        cur += (uint64_t)pl.nb * BUCKET * 4;
-        p.hdr = reinterpret_cast<uint64_t *>(cur);
-        cur += 2ull * pl.nb * 8;
+        p.slots = reinterpret_cast<uint32_t *>(cur);
+        cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
         p.bm = reinterpret_cast<uint32_t *>(cur);
         cur += 2ull * pl.bmw * 4;
         if (pl.G > 1) {

@@ -26,7 +26,6 @@ def _run(A, **kw):
 
 def _check_stats(s, n, H_np=None):
     assert s["aux_words"] <= s["aux_bound_words"]
-    assert s["attempts"] == s["attempts"]  # present
     if H_np is not None:
         selfl = int(np.sum(H_np == np.arange(n, dtype=np.uint64)))
         nonself = n - selfl
@@ -34,7 +33,9 @@ def _check_stats(s, n, H_np=None):
         assert s["attempts"] == nonself + s["retries"]
         if s["k"] > 0:
             assert s["rounds"] >= -(-nonself // s["k"])
-        assert s["rounds"] <= nonself + 64
+        # Each round either commits a swap (the top active one always wins)
+        # or only retires self-loops while consuming k fresh indices.
+        assert s["rounds"] <= nonself + -(-n // max(1, s["k"])) + 2
 
 
 def _host_records(n, eb, seed):
