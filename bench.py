@@ -26,12 +26,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 WORKLOAD = {"n": 1 << 30, "elem_bytes": 8, "eps": 0.5, "seed": 1}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rp_rounds_kernel_n2p30_int64_eps0.5_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2103_01216_amd", "csrc", "rp.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2103_01216_amd", "csrc", f)
+               for f in ("rp.hip", "rp_device.h")]
 
 
 def _src_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] over the sources the shuffle kernel is compiled from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic_bytes():

@@ -136,6 +136,81 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
 int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
                     uint64_t *out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent shuffles in one persistent launch.
+ *
+ * Each request is an independent call of the operation above on its own array
+ * (same semantics and the same auxiliary bound per request, floor(n^(1-eps))
+ * words, here held in the on-chip LDS of the lanes that run it).  Requests of
+ * one batch share one record size; n < 2^24 per request.  The batch is
+ * stream-ordered; completion can be observed without blocking.
+ */
+typedef struct rp_batch_request {
+    void *A;                 /* device records, permuted in place (caller-owned) */
+    uint64_t n;              /* number of records, < 2^24 */
+    uint32_t elem_bytes;     /* multiple of 4 in [4, 256]; equal for the batch */
+    uint32_t reserved;       /* 0 */
+    const uint64_t *H;       /* device targets (H[i] <= i) or NULL: seed mode */
+    uint64_t seed;           /* seed mode: H[i] = splitmix64(seed ^ i) mod (i+1) */
+    double eps;              /* in (0, 1) */
+} rp_batch_request;
+
+typedef struct rp_batch_result {
+    uint64_t rounds;         /* rounds run for this request */
+    uint64_t attempts;       /* swap attempts summed over its rounds */
+    int32_t status;          /* RP_OK, RP_EINVAL (some H[i] > i; A untouched),
+                                RP_ETIMEOUT */
+    uint32_t aux_words;      /* 8-byte words of round state it used */
+} rp_batch_result;
+
+/* Schedule of a batch launch (chosen by rp_batch_autotune, or defaults):
+ * requests with n >= wave_cutoff run one per workgroup, smaller ones one per
+ * wave; table_ratio_x16 = 16 * reservation slots per active swap;
+ * workgroups_per_cu = resident workgroups per compute unit. */
+typedef struct rp_batch_schedule {
+    uint32_t wave_cutoff;
+    uint32_t table_ratio_x16;
+    uint32_t workgroups_per_cu;
+    uint32_t tuned_ms_x1000;  /* out: best trial time in microseconds */
+} rp_batch_schedule;
+
+/*
+ * Choose a schedule for batches shaped like reqs (host array of count
+ * requests): times trial launches of candidate schedules on scratch copies of
+ * an evenly spaced sample of the requests (seed mode; the caller's arrays are
+ * not touched), waits for them, writes the fastest to *out (host) and makes it
+ * the default of later rp_batch_submit calls that pass no schedule.
+ * Returns RP_OK, RP_EINVAL, RP_ENOMEM.
+ */
+int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream,
+                      rp_batch_schedule *out);
+
+/*
+ * Enqueue a batch (reqs is a host array, copied before return; sched may be
+ * NULL for the tuned or default schedule).  Does not wait for the GPU.  Writes
+ * a batch id to *batch_id (host).  RP_EINVAL for a malformed request (no
+ * request runs then); requests whose H fails validation finish with status
+ * RP_EINVAL and untouched arrays while the rest of the batch runs.
+ */
+int rp_batch_submit(const rp_batch_request *reqs, uint32_t count,
+                    const rp_batch_schedule *sched, void *stream, uint64_t *batch_id);
+
+/* Non-blocking: *n_done (host, may be NULL) = finished requests; returns
+ * RP_OK when all are finished, RP_PENDING otherwise, RP_EINVAL for an unknown
+ * id. */
+int rp_batch_poll(uint64_t batch_id, uint32_t *n_done);
+
+/* Non-blocking: RP_OK if request `index` (caller's order) has finished and its
+ * array may be read by later stream work, RP_PENDING if not. */
+int rp_batch_request_done(uint64_t batch_id, uint32_t index);
+
+/* Waits for the batch and copies count results (caller's order) to out
+ * (host, may be NULL). */
+int rp_batch_results(uint64_t batch_id, rp_batch_result *out);
+
+/* Waits for the batch and frees its bookkeeping; the id becomes invalid. */
+int rp_batch_release(uint64_t batch_id);
+
 #ifdef __cplusplus
 }
 #endif

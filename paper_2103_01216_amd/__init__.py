@@ -166,3 +166,146 @@ def rp_seed_targets(idx, seed: int, stream=None):
     if rc != RP_OK:
         raise RpError(rc, "rp_seed_targets")
     return out
+
+
+# ------------------------------------------------------------------ batches
+
+class rp_batch_request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("elem_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("H", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("eps", ctypes.c_double)]
+
+
+class rp_batch_result(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("attempts", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("aux_words", ctypes.c_uint32)]
+
+
+class rp_batch_schedule(ctypes.Structure):
+    _fields_ = [("wave_cutoff", ctypes.c_uint32), ("table_ratio_x16", ctypes.c_uint32),
+                ("workgroups_per_cu", ctypes.c_uint32), ("tuned_ms_x1000", ctypes.c_uint32)]
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        u32, u64, vp, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+        L.rp_batch_autotune.restype = i32
+        L.rp_batch_autotune.argtypes = [ctypes.POINTER(rp_batch_request), u32, vp,
+                                        ctypes.POINTER(rp_batch_schedule)]
+        L.rp_batch_submit.restype = i32
+        L.rp_batch_submit.argtypes = [ctypes.POINTER(rp_batch_request), u32,
+                                      ctypes.POINTER(rp_batch_schedule), vp,
+                                      ctypes.POINTER(u64)]
+        L.rp_batch_poll.restype = i32
+        L.rp_batch_poll.argtypes = [u64, ctypes.POINTER(u32)]
+        L.rp_batch_request_done.restype = i32
+        L.rp_batch_request_done.argtypes = [u64, u32]
+        L.rp_batch_results.restype = i32
+        L.rp_batch_results.argtypes = [u64, ctypes.POINTER(rp_batch_result)]
+        L.rp_batch_release.restype = i32
+        L.rp_batch_release.argtypes = [u64]
+        L._batch_ready = True
+    return L
+
+
+def _requests(arrays, seeds, H, eps):
+    reqs = (rp_batch_request * len(arrays))()
+    for i, A in enumerate(arrays):
+        n, eb = _record_geometry(A)
+        h = None if H is None else H[i]
+        if h is not None and (not h.is_cuda or h.element_size() != 8 or h.numel() != n
+                              or not h.is_contiguous()):
+            raise ValueError("H[i] must be a contiguous device tensor of n 64-bit targets")
+        reqs[i].A = A.data_ptr() if n else None
+        reqs[i].n = n
+        reqs[i].elem_bytes = eb
+        reqs[i].reserved = 0
+        reqs[i].H = None if h is None else h.data_ptr()
+        reqs[i].seed = (0 if seeds is None else int(seeds[i])) & (2**64 - 1)
+        reqs[i].eps = eps
+    return reqs
+
+
+def _schedule_dict(s: rp_batch_schedule) -> dict:
+    return {f: int(getattr(s, f)) for f, _ in rp_batch_schedule._fields_}
+
+
+class Batch:
+    """A submitted batch; keeps its tensors alive until released."""
+
+    def __init__(self, bid: int, keep):
+        self.id = bid
+        self._keep = keep
+        self._released = False
+
+    def poll(self):
+        """(all_done, n_done) without blocking."""
+        n = ctypes.c_uint32(0)
+        rc = _batch_lib().rp_batch_poll(self.id, ctypes.byref(n))
+        if rc not in (RP_OK, RP_PENDING):
+            raise RpError(rc, "rp_batch_poll")
+        return rc == RP_OK, int(n.value)
+
+    def request_done(self, i: int) -> bool:
+        rc = _batch_lib().rp_batch_request_done(self.id, i)
+        if rc not in (RP_OK, RP_PENDING):
+            raise RpError(rc, "rp_batch_request_done")
+        return rc == RP_OK
+
+    def results(self):
+        count = len(self._keep[0])
+        out = (rp_batch_result * max(1, count))()
+        rc = _batch_lib().rp_batch_results(self.id, out)
+        if rc != RP_OK:
+            raise RpError(rc, "rp_batch_results")
+        return [{"rounds": int(r.rounds), "attempts": int(r.attempts),
+                 "status": int(r.status), "aux_words": int(r.aux_words)}
+                for r in out[:count]]
+
+    def release(self):
+        if not self._released:
+            rc = _batch_lib().rp_batch_release(self.id)
+            self._released = True
+            if rc != RP_OK:
+                raise RpError(rc, "rp_batch_release")
+
+
+def rp_batch_submit(arrays, *, seeds=None, H=None, eps: float = 0.5,
+                    schedule: dict | None = None, stream=None) -> Batch:
+    """Enqueue one shuffle per tensor in `arrays` as a single persistent launch.
+
+    seeds: per-request seeds (seed mode) or None with H: per-request device
+    target tensors.  schedule: dict with wave_cutoff, table_ratio_x16,
+    workgroups_per_cu, or None for the tuned/default schedule.
+    """
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    reqs = _requests(arrays, seeds, H, eps)
+    sched = None
+    if schedule is not None:
+        sched = rp_batch_schedule(schedule["wave_cutoff"], schedule["table_ratio_x16"],
+                                  schedule["workgroups_per_cu"], 0)
+    bid = ctypes.c_uint64(0)
+    rc = _batch_lib().rp_batch_submit(reqs, len(arrays),
+                                      ctypes.byref(sched) if sched is not None else None,
+                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(bid))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_batch_submit")
+    return Batch(int(bid.value), (list(arrays), H))
+
+
+def rp_batch_autotune(arrays, *, seeds=None, eps: float = 0.5, stream=None) -> dict:
+    """Pick a schedule for batches shaped like `arrays` (trial runs on scratch)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    reqs = _requests(arrays, seeds, None, eps)
+    out = rp_batch_schedule()
+    rc = _batch_lib().rp_batch_autotune(reqs, len(arrays),
+                                        ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_batch_autotune")
+    return _schedule_dict(out)

@@ -1,4 +1,4 @@
-"""Compile the HIP library (csrc/rp.hip) into librp.so beside this file.
+"""Compile the HIP library (csrc/*.hip) into librp.so beside this file.
 
 Run as ``python -m paper_2103_01216_amd.build``.  hipcc cross-compiles for
 gfx950 without a GPU.  Packed FP32 instructions are disabled for all device
@@ -12,7 +12,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "rp.hip")
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("rp.hip", "rp_batch.hip")]
 LIB = os.path.join(PKG, "librp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -29,7 +29,8 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, SRC]
+    srcs = [f for f in SRCS if os.path.exists(f)]
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,0 +1,803 @@
+// Batched form of librp: many independent in-place shuffles in one persistent
+// launch.
+//
+// Every request is the Knuth shuffle of Section 4.1 (Gu, Obeya, Shun,
+// "Parallel In-Place Algorithms: Theory and Practice") on its own array, run
+// with the same round structure as rp.hip (relaxed-PIP rounds over the first
+// k unfinished swaps, RP-Final single reservation with a dense window for the
+// round's consecutive keys), but every request is owned by one group of
+// lanes and never synchronises with another group:
+//   * workgroup mode: the whole workgroup runs one request; the hashed
+//     reservation array and the dense window live in the workgroup's LDS and
+//     rounds are separated by workgroup barriers;
+//   * wave mode: one wave runs one small request in its own quarter of the
+//     LDS; a wave executes in order, so rounds need no barrier at all.
+// Requests are sorted by size, largest first; the largest ones are claimed by
+// workgroups from one counter, the rest by single waves from another (longest
+// job first keeps the tail short).  The size that separates the two modes, the
+// table ratio and the number of resident workgroups form the schedule, chosen
+// by rp_batch_autotune from timed trial runs on scratch copies of a sample of
+// the batch.
+//
+// Auxiliary space per request: the LDS words its round state uses (slots and
+// both dense-window parities), at most floor(n^(1-eps)) 8-byte words.
+// Completion is signalled per request through host-visible memory, so the
+// caller can poll without blocking.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "rp.h"
+#include "rp_device.h"
+
+namespace {
+
+using namespace rpdev;
+
+constexpr int BWG = 256;                 // threads per workgroup
+constexpr int BWAVES = BWG / 64;
+constexpr int BM = 8;                    // swap slots per lane (maximum)
+constexpr uint32_t LDS_WORDS = 8192;     // 32 KB of round state per workgroup
+constexpr uint32_t WAVE_WORDS = LDS_WORDS / BWAVES;
+constexpr uint32_t BATCH_MAX_N = 1u << 24;  // ranks fit 24 bits without a throttle
+
+struct BatchReq {
+    unsigned char *A;
+    const uint64_t *H;     // nullptr: seed mode
+    uint64_t seed;
+    uint32_t n, eb;
+    uint32_t k;            // active-swap capacity
+    uint32_t T;            // reservation slots (LDS words)
+    uint32_t bmw;          // dense-window words per parity
+    uint32_t wg_mode;      // 1: workgroup, 0: wave
+    uint32_t orig;         // index in the caller's array
+    uint32_t invalid;      // set on the device when some H[i] > i
+};
+
+struct BatchParams {
+    BatchReq *reqs;
+    uint32_t count;
+    uint32_t n_wg;          // reqs[0 .. n_wg) run in workgroup mode
+    uint32_t *claims;       // [0]: next workgroup request, [1]: next wave request
+    rp_batch_result *res;   // indexed by the caller's order
+    uint32_t *done_flags;   // host-visible: per request (caller's order)
+};
+
+// ------------------------------------------------------------ lane groups
+
+// Workgroup: 256 lanes, LDS scratch shared, barrier = __syncthreads.
+struct WGGroup {
+    uint32_t *lds;
+    uint32_t *sh_scan;  // BWAVES words
+    __device__ uint32_t nlanes() const { return BWG; }
+    __device__ uint32_t lane() const { return threadIdx.x; }
+    __device__ void sync() const { __syncthreads(); }
+    // Exclusive prefix of x over the group; *total = sum.  Contains a
+    // barrier, which also separates one round from the next.
+    __device__ uint32_t excl_scan(uint32_t x, uint32_t *total) const
+    {
+        const uint32_t wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const uint32_t xi = wave_incl_scan(x);
+        if (l == 63)
+            sh_scan[wave] = xi;
+        __syncthreads();
+        uint32_t below = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < BWAVES; i++) {
+            const uint32_t v = sh_scan[i];
+            below += ((uint32_t)i < wave) ? v : 0u;
+            tot += v;
+        }
+        *total = __builtin_amdgcn_readfirstlane(tot);
+        return below + xi - x;
+    }
+};
+
+// One wave, 64 lanes, executing in order: LDS and global accesses of its
+// lanes are ordered by program order, so "sync" is only a compiler fence.
+struct WaveGroup {
+    uint32_t *lds;
+    __device__ uint32_t nlanes() const { return 64; }
+    __device__ uint32_t lane() const { return threadIdx.x & 63; }
+    __device__ void sync() const { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
+    __device__ uint32_t excl_scan(uint32_t x, uint32_t *total) const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        const uint32_t xi = wave_incl_scan(x);
+        *total = __builtin_amdgcn_readlane(xi, 63);
+        return xi - x;
+    }
+};
+
+__device__ __forceinline__ uint32_t breq_target(const BatchReq &r, uint32_t s)
+{
+    return r.H ? (uint32_t)r.H[s] : seed_target(r.seed, s);
+}
+
+__device__ __forceinline__ uint32_t lds_ld(const uint32_t *p)
+{
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Records moved with plain loads and stores: every access to A comes from the
+// lanes of one group, which see each other's writes after the group's sync.
+template <int EB> struct PRec;
+template <> struct PRec<4> {
+    uint32_t w;
+    __device__ void load(const unsigned char *A, uint32_t i)
+    { w = reinterpret_cast<const uint32_t *>(A)[i]; }
+    __device__ void store(unsigned char *A, uint32_t i) const
+    { reinterpret_cast<uint32_t *>(A)[i] = w; }
+};
+template <> struct PRec<8> {
+    uint64_t w;
+    __device__ void load(const unsigned char *A, uint32_t i)
+    { w = reinterpret_cast<const uint64_t *>(A)[i]; }
+    __device__ void store(unsigned char *A, uint32_t i) const
+    { reinterpret_cast<uint64_t *>(A)[i] = w; }
+};
+
+__device__ __forceinline__ void pswap_generic(unsigned char *A, uint32_t eb,
+                                              uint32_t a, uint32_t b)
+{
+    uint32_t *pa = reinterpret_cast<uint32_t *>(A + (uint64_t)a * eb);
+    uint32_t *pb = reinterpret_cast<uint32_t *>(A + (uint64_t)b * eb);
+    for (uint32_t j = 0; j < eb / 4; j++) {
+        const uint32_t x = pa[j], y = pb[j];
+        pa[j] = y;
+        pb[j] = x;
+    }
+}
+
+// Run one request on group g.  Returns (rounds, attempts) through pointers
+// valid on every lane.
+template <int EB, typename Group>
+__device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_rounds,
+                            uint64_t *rounds_out, uint64_t *attempts_out,
+                            uint32_t *status_out)
+{
+    const uint32_t L = g.nlanes(), lane = g.lane();
+    const uint32_t T = r.T, bmw = r.bmw, W = r.bmw * 32u;
+    if (T == 0) {
+        // The bound holds no reservation state: k = 1, and a single active
+        // swap always commits, so the rounds are the sequential loop.
+        uint64_t rounds = 0;
+        if (lane == 0) {
+            for (uint32_t i = r.n; i-- > 0;) {
+                const uint32_t h = breq_target(r, i);
+                if (h == i)
+                    continue;
+                pswap_generic(r.A, r.eb, i, h);
+                rounds++;
+            }
+        }
+        g.sync();
+        *rounds_out = rounds;
+        *attempts_out = rounds;
+        *status_out = 0;
+        return;
+    }
+    uint32_t *slots = g.lds;
+    uint32_t *bm = g.lds + T;
+    g.sync();
+    for (uint32_t i = lane; i < T + 2 * bmw; i += L)
+        lds_st(&g.lds[i], 0u);
+    g.sync();
+
+    uint32_t src[BM], tgt[BM];
+    bool usable[BM];
+#pragma unroll
+    for (int m = 0; m < BM; m++) {
+        usable[m] = ((uint64_t)m * L + lane) < r.k;
+        src[m] = EMPTY;
+        tgt[m] = 0;
+    }
+    uint32_t cursor = r.n;
+    uint64_t rounds = 0, attempts = 0;
+    uint32_t status = 0;
+    for (;;) {
+        uint32_t f = 0, a = 0;
+#pragma unroll
+        for (int m = 0; m < BM; m++) {
+            f += (usable[m] && src[m] == EMPTY) ? 1u : 0u;
+            a += (src[m] != EMPTY) ? 1u : 0u;
+        }
+        uint32_t tot;
+        const uint32_t x = (a << 16) | f;
+        const uint32_t lane_off = g.excl_scan(x, &tot) & 0xFFFFu;
+        const uint32_t totF = tot & 0xFFFFu, totA = tot >> 16;
+        if (cursor == 0 && totA == 0)
+            break;
+        if (rounds >= max_rounds) {
+            status = (uint32_t)(-RP_ETIMEOUT);
+            break;
+        }
+        const uint32_t take = min(totF, cursor);
+        const uint32_t cnew = cursor - take;
+        const uint32_t par = (uint32_t)(rounds & 1);
+        const uint32_t tag = (uint32_t)(rounds & 255);
+        if (tag == 0 && rounds > 0) {
+            // Tags restart: empty the slot array (every check of the last
+            // round finished before the scan's barrier).
+            for (uint32_t i = lane; i < T; i += L)
+                lds_st(&slots[i], 0u);
+            g.sync();
+        }
+        // refill
+        uint32_t j = lane_off;
+#pragma unroll
+        for (int m = 0; m < BM; m++) {
+            if (usable[m] && src[m] == EMPTY) {
+                const uint32_t ord = j++;
+                if (ord < take) {
+                    const uint32_t s = cursor - 1u - ord;
+                    const uint32_t h = breq_target(r, s);
+                    if (h != s) {
+                        src[m] = s;
+                        tgt[m] = h;
+                    }
+                }
+            }
+        }
+        PRec<EB == 0 ? 4 : EB> r_s[BM], r_h[BM];
+        if (EB != 0) {
+#pragma unroll
+            for (int m = 0; m < BM; m++)
+                if (src[m] != EMPTY) {
+                    r_s[m].load(r.A, src[m]);
+                    r_h[m].load(r.A, tgt[m]);
+                }
+        }
+        // reserve
+#pragma unroll
+        for (int m = 0; m < BM; m++) {
+            if (src[m] != EMPTY) {
+                attempts++;
+                const uint32_t v = (tag << RANKB) | (src[m] - cnew);
+                __hip_atomic_fetch_max(&slots[slot1(tgt[m], T)], v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint32_t d = tgt[m] - cnew;
+                if (tgt[m] >= cnew && d < W)
+                    __hip_atomic_fetch_or(&bm[par * bmw + (d >> 5)], 1u << (d & 31u),
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        for (uint32_t i = lane; i < bmw; i += L)
+            lds_st(&bm[(par ^ 1u) * bmw + i], 0u);
+        g.sync();
+        // commit
+#pragma unroll
+        for (int m = 0; m < BM; m++) {
+            if (src[m] == EMPTY)
+                continue;
+            const uint32_t s = src[m], h = tgt[m];
+            const uint32_t ds = s - cnew;
+            const uint32_t v = (tag << RANKB) | ds;
+            bool win = lds_ld(&slots[slot1(h, T)]) == v;
+            if (ds < W)
+                win = win && !((lds_ld(&bm[par * bmw + (ds >> 5)]) >> (ds & 31u)) & 1u);
+            else
+                win = win && lds_ld(&slots[slot1(s, T)]) <= v;
+            if (win) {
+                if (EB != 0) {
+                    r_h[m].store(r.A, s);
+                    r_s[m].store(r.A, h);
+                } else {
+                    pswap_generic(r.A, r.eb, s, h);
+                }
+                src[m] = EMPTY;
+            }
+        }
+        cursor = cnew;
+        rounds++;
+    }
+    *rounds_out = rounds;
+    *attempts_out = attempts;
+    *status_out = status;
+}
+
+__device__ __forceinline__ uint64_t sum_over_group_wg(uint64_t v, uint64_t *sh)
+{
+    v = wave_sum64(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < BWAVES; i++)
+        t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ void publish(const BatchParams &bp, const BatchReq &r,
+                                        uint64_t rounds, uint64_t attempts,
+                                        uint32_t status)
+{
+    rp_batch_result out;
+    out.rounds = rounds;
+    out.attempts = attempts;
+    out.status = r.invalid ? RP_EINVAL : status ? -(int32_t)status : RP_OK;
+    out.aux_words = (uint32_t)(((uint64_t)(r.T + 2 * r.bmw) * 4 + 7) / 8);
+    bp.res[r.orig] = out;
+    // Make the request's records and result visible beyond the device, then
+    // raise its completion flag.  Host memory is only ever written with
+    // stores (no read-modify-write atomics across the host link).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __hip_atomic_store(&bp.done_flags[r.orig], 1u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <int EB>
+__global__ __launch_bounds__(BWG) void rp_batch_kernel(BatchParams bp)
+{
+    __shared__ uint32_t lds[LDS_WORDS];
+    __shared__ uint32_t sh_scan[BWAVES];
+    __shared__ uint64_t sh_red[BWAVES];
+    __shared__ uint32_t sh_claim;
+
+    // Every value that steers these loops is wave-uniform (held in scalar
+    // registers), and the single-lane claim and publish steps are closed by
+    // a barrier before the loop's back edge.  Otherwise the compiler may merge
+    // the publish of one iteration with the claim of the next into a region
+    // that parks the claiming lane outside the loop while the other lanes
+    // keep re-running the previous request.
+
+    // Workgroup mode: the largest requests, one per workgroup.
+    WGGroup wg{lds, sh_scan};
+    for (;;) {
+        if (threadIdx.x == 0)
+            sh_claim = __hip_atomic_fetch_add(&bp.claims[0], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t idx = __builtin_amdgcn_readfirstlane(sh_claim);
+        __syncthreads();
+        if (idx >= bp.n_wg)
+            break;
+        const BatchReq r = bp.reqs[idx];
+        uint64_t rounds = 0, attempts = 0;
+        uint32_t status = 0;
+        if (r.n > 1 && !r.invalid)
+            run_request<EB>(wg, r, (uint64_t)r.n + 64, &rounds, &attempts, &status);
+        attempts = sum_over_group_wg(attempts, sh_red);
+        rounds = sum_over_group_wg(r.T == 0 ? rounds : (threadIdx.x == 0 ? rounds : 0), sh_red);
+        if (threadIdx.x == 0)
+            publish(bp, r, rounds, attempts, status);
+        __syncthreads();
+    }
+    // Wave mode: the rest, one per wave, each in its quarter of the LDS.
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    WaveGroup wv{lds + wave * WAVE_WORDS};
+    for (;;) {
+        // Every lane adds (1 on lane 0, 0 elsewhere); lane 0's old value is
+        // the claim.  No lane-divergent branch around the claim.
+        const uint32_t got = __hip_atomic_fetch_add(&bp.claims[1], lane == 0 ? 1u : 0u,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t idx = bp.n_wg + __builtin_amdgcn_readlane(got, 0);
+        if (idx >= bp.count)
+            break;
+        const BatchReq r = bp.reqs[idx];
+        uint64_t rounds = 0, attempts = 0;
+        uint32_t status = 0;
+        if (r.n > 1 && !r.invalid)
+            run_request<EB>(wv, r, (uint64_t)r.n + 64, &rounds, &attempts, &status);
+        attempts = wave_sum64(attempts);
+        rounds = wave_sum64(lane == 0 ? rounds : 0);
+        if (lane == 0)
+            publish(bp, r, rounds, attempts, status);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Before the batch: reset the claim counters, and mark every explicit-target
+// request with some H[i] > i as invalid (it is then skipped and its array is
+// left untouched).  One workgroup per request.
+__global__ void rp_batch_prepare_kernel(BatchReq *reqs, uint32_t count, uint32_t *claims)
+{
+    // The claim counters are later advanced by atomic adds: reset them with an
+    // atomic too (a plain store and RMW atomics on one word are not ordered).
+    if (blockIdx.x == 0 && threadIdx.x < 16)
+        (void)__hip_atomic_exchange(&claims[threadIdx.x], 0u, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
+        const BatchReq &r = reqs[q];
+        if (r.H == nullptr)
+            continue;
+        bool bad = false;
+        for (uint32_t i = threadIdx.x; i < r.n; i += blockDim.x)
+            bad = bad || (r.H[i] > i);
+        if (bad)
+            __hip_atomic_store(&reqs[q].invalid, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+int env_or(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+struct Batch {
+    hipStream_t stream = nullptr;
+    uint32_t count = 0;
+    void *dev = nullptr;            // reqs | claims
+    rp_batch_result *res = nullptr; // host-visible (pinned)
+    uint32_t *done = nullptr;       // host-visible (pinned): [1..count] flags
+    BatchReq *staging = nullptr;    // pinned copy of the descriptors
+};
+
+std::mutex g_bmu;
+std::map<uint64_t, Batch> g_batches;
+uint64_t g_next_id = 1;
+
+// Round-state words for a request at the given table ratio and lane count,
+// within the LDS words available; k = 0 means the request needs no rounds.
+void plan_request(uint64_t n, double eps, double ratio, uint32_t lanes,
+                  uint32_t lds_words, uint32_t *k, uint32_t *T, uint32_t *bmw)
+{
+    *k = *T = *bmw = 0;
+    if (n <= 1)
+        return;
+    const uint64_t bound_bytes = rp_aux_bound_words(n, eps) * 8;
+    const uint64_t cap_words = std::min<uint64_t>(bound_bytes / 4, lds_words);
+    uint64_t best = 1;
+    uint64_t lo = 1, hi = std::min<uint64_t>((uint64_t)lanes * BM, n);
+    auto words = [&](uint64_t kk) {
+        const uint64_t t = std::max<uint64_t>(1, (uint64_t)std::ceil(ratio * (double)kk));
+        const uint64_t b = std::max<uint64_t>(1, (2 * kk + 31) / 32);
+        return t + 2 * b;
+    };
+    while (lo <= hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (words(mid) <= cap_words) {
+            best = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    *k = (uint32_t)best;
+    *T = (uint32_t)std::max<uint64_t>(1, (uint64_t)std::ceil(ratio * (double)best));
+    *bmw = (uint32_t)std::max<uint64_t>(1, (2 * best + 31) / 32);
+    if (words(best) > cap_words) {
+        // Not even k = 1 with a table fits: run the request with k = 1 and no
+        // round state at all (one active swap always commits).
+        *k = 1;
+        *T = 0;
+        *bmw = 0;
+    }
+}
+
+bool valid_request(const rp_batch_request &q)
+{
+    if (!(q.eps > 0.0 && q.eps < 1.0))
+        return false;
+    if (q.elem_bytes == 0 || (q.elem_bytes & 3u) || q.elem_bytes > 256)
+        return false;
+    if (q.n >= BATCH_MAX_N)
+        return false;
+    if (q.A == nullptr && q.n > 1)
+        return false;
+    return true;
+}
+
+rp_batch_schedule default_schedule()
+{
+    rp_batch_schedule s{};
+    s.wave_cutoff = (uint32_t)env_or("RP_BATCH_CUTOFF", 1 << 14);
+    s.table_ratio_x16 = (uint32_t)env_or("RP_BATCH_RATIO16", 16);
+    s.workgroups_per_cu = (uint32_t)env_or("RP_BATCH_WPC", 4);
+    return s;
+}
+
+std::mutex g_tmu;
+bool g_tuned = false;
+rp_batch_schedule g_tuned_sched{};
+
+using BatchKernelFn = void (*)(BatchParams);
+
+BatchKernelFn pick_batch_kernel(uint32_t eb)
+{
+    if (eb == 4) return rp_batch_kernel<4>;
+    if (eb == 8) return rp_batch_kernel<8>;
+    return rp_batch_kernel<0>;
+}
+
+int launch_batch(const rp_batch_request *reqs, uint32_t count,
+                 const rp_batch_schedule &sched, hipStream_t stream, Batch *b)
+{
+    b->stream = stream;
+    b->count = count;
+    const double ratio = std::max(1u, sched.table_ratio_x16) / 16.0;
+    uint32_t eb = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        if (!valid_request(reqs[i]))
+            return RP_EINVAL;
+        if (eb == 0)
+            eb = reqs[i].elem_bytes;
+        else if (eb != reqs[i].elem_bytes)
+            return RP_EINVAL;  // one record size per batch
+    }
+    // Order: largest first; workgroup mode for n >= cutoff.
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t c) { return reqs[a].n > reqs[c].n; });
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->staging),
+                      sizeof(BatchReq) * std::max(1u, count)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&b->res),
+                      sizeof(rp_batch_result) * std::max(1u, count)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&b->done),
+                      sizeof(uint32_t) * (count + 1), hipHostMallocCoherent) != hipSuccess)
+        return RP_ENOMEM;
+    std::memset(b->done, 0, sizeof(uint32_t) * (count + 1));
+    std::memset(b->res, 0, sizeof(rp_batch_result) * std::max(1u, count));
+    uint32_t n_wg = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        const rp_batch_request &q = reqs[order[i]];
+        const bool wgm = q.n >= sched.wave_cutoff;
+        n_wg += wgm ? 1u : 0u;
+        BatchReq &r = b->staging[i];
+        r.A = static_cast<unsigned char *>(q.A);
+        r.H = q.H;
+        r.seed = q.seed;
+        r.n = (uint32_t)q.n;
+        r.eb = q.elem_bytes;
+        plan_request(q.n, q.eps, ratio, wgm ? BWG : 64, wgm ? LDS_WORDS : WAVE_WORDS,
+                     &r.k, &r.T, &r.bmw);
+        r.wg_mode = wgm ? 1u : 0u;
+        r.orig = order[i];
+        r.invalid = 0;
+    }
+    // Sorted order puts every workgroup-mode request first.
+    const size_t bytes = sizeof(BatchReq) * std::max(1u, count) + 64;
+    if (hipMallocAsync(&b->dev, bytes, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RP_ENOMEM;
+    }
+    BatchReq *dreqs = static_cast<BatchReq *>(b->dev);
+    uint32_t *claims = reinterpret_cast<uint32_t *>(
+        static_cast<unsigned char *>(b->dev) + sizeof(BatchReq) * std::max(1u, count));
+    if (count > 0 && hipMemcpyAsync(dreqs, b->staging, sizeof(BatchReq) * count,
+                                    hipMemcpyHostToDevice, stream) != hipSuccess)
+        return RP_EDEVICE;
+    rp_batch_prepare_kernel<<<std::max(1u, std::min(count, 4096u)), 256, 0, stream>>>(
+        dreqs, count, claims);
+    if (hipGetLastError() != hipSuccess)
+        return RP_EDEVICE;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+    }
+    const BatchKernelFn fn = pick_batch_kernel(eb);
+    int occ = 1;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, reinterpret_cast<const void *>(fn), BWG, 0);
+    const uint32_t wpc = std::max(1u, std::min<uint32_t>(sched.workgroups_per_cu,
+                                                         (uint32_t)std::max(occ, 1)));
+    uint32_t grid = (uint32_t)cus * wpc;
+    BatchParams bp{};
+    bp.reqs = dreqs;
+    bp.count = count;
+    bp.n_wg = n_wg;
+    bp.claims = claims;
+    bp.res = b->res;
+    bp.done_flags = b->done + 1;
+    if (count > 0) {
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(BWG), 0, stream, bp);
+        if (hipGetLastError() != hipSuccess)
+            return RP_EDEVICE;
+    }
+    return RP_OK;
+}
+
+void release_batch(Batch &b)
+{
+    if (b.dev)
+        (void)hipFreeAsync(b.dev, b.stream);
+    if (b.staging || b.res || b.done)
+        (void)hipStreamSynchronize(b.stream);
+    if (b.staging)
+        (void)hipHostFree(b.staging);
+    if (b.res)
+        (void)hipHostFree(b.res);
+    if (b.done)
+        (void)hipHostFree(b.done);
+    b = Batch{};
+}
+
+}  // namespace
+
+extern "C" {
+
+int rp_batch_submit(const rp_batch_request *reqs, uint32_t count,
+                    const rp_batch_schedule *sched, void *stream_,
+                    uint64_t *batch_id)
+{
+    if (batch_id == nullptr || (reqs == nullptr && count > 0))
+        return RP_EINVAL;
+    rp_batch_schedule s;
+    if (sched) {
+        s = *sched;
+    } else {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        s = g_tuned ? g_tuned_sched : default_schedule();
+    }
+    Batch b;
+    const int rc = launch_batch(reqs, count, s, reinterpret_cast<hipStream_t>(stream_), &b);
+    if (rc != RP_OK) {
+        release_batch(b);
+        return rc;
+    }
+    std::lock_guard<std::mutex> lk(g_bmu);
+    *batch_id = g_next_id++;
+    g_batches[*batch_id] = b;
+    return RP_OK;
+}
+
+int rp_batch_poll(uint64_t batch_id, uint32_t *n_done)
+{
+    std::lock_guard<std::mutex> lk(g_bmu);
+    auto it = g_batches.find(batch_id);
+    if (it == g_batches.end())
+        return RP_EINVAL;
+    const Batch &b = it->second;
+    uint32_t d = 0;
+    for (uint32_t i = 0; i < b.count; i++)
+        d += __atomic_load_n(b.done + 1 + i, __ATOMIC_ACQUIRE) ? 1u : 0u;
+    if (n_done)
+        *n_done = d;
+    return d >= b.count ? RP_OK : RP_PENDING;
+}
+
+int rp_batch_request_done(uint64_t batch_id, uint32_t index)
+{
+    std::lock_guard<std::mutex> lk(g_bmu);
+    auto it = g_batches.find(batch_id);
+    if (it == g_batches.end() || index >= it->second.count)
+        return RP_EINVAL;
+    return __atomic_load_n(it->second.done + 1 + index, __ATOMIC_ACQUIRE) ? RP_OK
+                                                                           : RP_PENDING;
+}
+
+int rp_batch_results(uint64_t batch_id, rp_batch_result *out)
+{
+    Batch b;
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        auto it = g_batches.find(batch_id);
+        if (it == g_batches.end())
+            return RP_EINVAL;
+        b = it->second;
+    }
+    if (hipStreamSynchronize(b.stream) != hipSuccess)
+        return RP_EDEVICE;
+    if (out)
+        std::memcpy(out, b.res, sizeof(rp_batch_result) * b.count);
+    return RP_OK;
+}
+
+int rp_batch_release(uint64_t batch_id)
+{
+    Batch b;
+    {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        auto it = g_batches.find(batch_id);
+        if (it == g_batches.end())
+            return RP_EINVAL;
+        b = it->second;
+        g_batches.erase(it);
+    }
+    release_batch(b);
+    return RP_OK;
+}
+
+int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream_,
+                      rp_batch_schedule *out)
+{
+    if (reqs == nullptr || count == 0)
+        return RP_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    for (uint32_t i = 0; i < count; i++)
+        if (!valid_request(reqs[i]))
+            return RP_EINVAL;
+    // Sample: every request when the batch is small, else an evenly spaced
+    // subset of the size-sorted batch (the same size mix), on scratch arrays
+    // in seed mode so that the caller's arrays are never touched.
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t c) { return reqs[a].n > reqs[c].n; });
+    const uint32_t want = std::min<uint32_t>(count, (uint32_t)env_or("RP_TUNE_SAMPLE", 512));
+    std::vector<rp_batch_request> sample;
+    uint64_t elems = 0;
+    for (uint32_t i = 0; i < want; i++) {
+        rp_batch_request q = reqs[order[(uint64_t)i * count / want]];
+        q.H = nullptr;
+        elems += q.n;
+        sample.push_back(q);
+    }
+    const uint32_t eb = sample[0].elem_bytes;
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, std::max<uint64_t>(elems * eb, 64)) != hipSuccess)
+        return RP_ENOMEM;
+    if (hipMemsetAsync(scratch, 0, std::max<uint64_t>(elems * eb, 64), stream) != hipSuccess) {
+        (void)hipFree(scratch);
+        return RP_EDEVICE;
+    }
+    uint64_t off = 0;
+    for (auto &q : sample) {
+        q.A = static_cast<unsigned char *>(scratch) + off * eb;
+        off += q.n;
+    }
+    const uint32_t cutoffs[] = {1u << 10, 1u << 12, 1u << 14, 1u << 16, 1u << 18, BATCH_MAX_N};
+    const uint32_t ratios[] = {12, 16, 24};
+    const uint32_t wpcs[] = {2, 4, 8};
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    rp_batch_schedule best = default_schedule();
+    for (uint32_t c : cutoffs)
+        for (uint32_t r16 : ratios)
+            for (uint32_t w : wpcs) {
+                rp_batch_schedule s{};
+                s.wave_cutoff = c;
+                s.table_ratio_x16 = r16;
+                s.workgroups_per_cu = w;
+                float tot = 0.f;
+                bool ok = true;
+                for (int rep = 0; rep < 2 && ok; rep++) {
+                    Batch b;
+                    (void)hipEventRecord(e0, stream);
+                    ok = launch_batch(sample.data(), (uint32_t)sample.size(), s, stream, &b) == RP_OK;
+                    (void)hipEventRecord(e1, stream);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (rep == 1)
+                        tot = ms;  // the first run is a warm-up
+                    release_batch(b);
+                }
+                if (ok && tot < best_ms) {
+                    best_ms = tot;
+                    best = s;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    best.tuned_ms_x1000 = (uint32_t)std::min<double>(4e9, best_ms * 1000.0);
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_tuned = true;
+        g_tuned_sched = best;
+    }
+    if (out)
+        *out = best;
+    return RP_OK;
+}
+
+}  // extern "C"

@@ -89,3 +89,9 @@ def adversarial_targets(n: int, kind: str) -> np.ndarray:
     else:
         raise ValueError(kind)
     return h.astype(np.uint64)
+
+
+def batch_sizes(count: int, lo_log2: float, hi_log2: float, seed: int) -> np.ndarray:
+    """Log-uniform sizes n = floor(2^U), U ~ Uniform[lo_log2, hi_log2)."""
+    rng = np.random.default_rng(seed)
+    return np.floor(2.0 ** rng.uniform(lo_log2, hi_log2, size=count)).astype(np.int64)

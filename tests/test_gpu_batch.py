@@ -1,0 +1,149 @@
+"""GPU parity of the batched form (rp_batch_*) against the CPU oracle.
+
+Each request of a batch is an independent Knuth shuffle; every result must
+equal the oracle's shuffle of the same array with the same targets, whatever
+the schedule (wave/workgroup cutoff, table ratio, resident workgroups).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2103_01216_amd as rp
+from paper_2103_01216_amd import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _oracle(n, seed, dtype=np.int32):
+    want = np.arange(n, dtype=dtype)
+    oracle.knuth_shuffle_seed(want, seed)
+    return want
+
+
+def _run_batch(arrays, seeds, eps=0.5, schedule=None, H=None):
+    b = rp.rp_batch_submit(arrays, seeds=seeds, H=H, eps=eps, schedule=schedule)
+    res = b.results()
+    done, nd = b.poll()
+    assert done and nd == len(arrays)
+    assert all(b.request_done(i) for i in range(len(arrays)))
+    b.release()
+    return res
+
+
+SCHEDULES = [None,
+             {"wave_cutoff": 1 << 24, "table_ratio_x16": 16, "workgroups_per_cu": 4},
+             {"wave_cutoff": 0, "table_ratio_x16": 16, "workgroups_per_cu": 2},
+             {"wave_cutoff": 1 << 12, "table_ratio_x16": 24, "workgroups_per_cu": 8},
+             {"wave_cutoff": 1 << 10, "table_ratio_x16": 12, "workgroups_per_cu": 1}]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_mixed_batch_matches_oracle(sched):
+    sizes = workloads.batch_sizes(96, 2, 16, 7)
+    sizes[:4] = [0, 1, 2, 3]
+    seeds = [1000 + i for i in range(len(sizes))]
+    arrays = [torch.arange(int(n), dtype=torch.int32, device=DEV) for n in sizes]
+    res = _run_batch(arrays, seeds, schedule=sched)
+    for i, n in enumerate(sizes):
+        assert res[i]["status"] == 0
+        assert res[i]["aux_words"] <= max(1, rp.rp_aux_bound_words(int(max(n, 1)), 0.5))
+        assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(n), seeds[i])), (i, n)
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.5, 0.9])
+def test_batch_eps(eps):
+    sizes = workloads.batch_sizes(40, 4, 15, 11)
+    seeds = [77 * i + 5 for i in range(len(sizes))]
+    arrays = [torch.arange(int(n), dtype=torch.int32, device=DEV) for n in sizes]
+    res = _run_batch(arrays, seeds, eps=eps)
+    for i, n in enumerate(sizes):
+        assert res[i]["status"] == 0
+        assert res[i]["aux_words"] <= rp.rp_aux_bound_words(int(n), eps)
+        assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(n), seeds[i]))
+
+
+@pytest.mark.parametrize("eb", [8, 16, 64])
+def test_batch_record_sizes(eb):
+    sizes = workloads.batch_sizes(24, 3, 14, 5)
+    seeds = list(range(len(sizes)))
+    rng = np.random.default_rng(eb)
+    host = [rng.integers(0, 2**32, size=(int(n), eb // 4), dtype=np.uint32) for n in sizes]
+    arrays = [torch.from_numpy(h.view(np.int32)).to(DEV) for h in host]
+    res = _run_batch(arrays, seeds)
+    for i, n in enumerate(sizes):
+        want = host[i].copy()
+        oracle.knuth_shuffle_seed(want, seeds[i])
+        assert res[i]["status"] == 0
+        assert np.array_equal(arrays[i].cpu().numpy().view(np.uint32), want)
+
+
+def test_batch_explicit_targets_and_invalid_request():
+    sizes = [1000, 5000, 300, 20000]
+    Hs, arrays = [], []
+    for i, n in enumerate(sizes):
+        H = workloads.uniform_targets(n, 40 + i)
+        if i == 2:
+            H[150] = 151  # invalid
+        Hs.append(torch.from_numpy(H.view(np.int64)).to(DEV))
+        arrays.append(torch.arange(n, dtype=torch.int32, device=DEV))
+    res = _run_batch(arrays, None, H=Hs)
+    for i, n in enumerate(sizes):
+        got = arrays[i].cpu().numpy()
+        if i == 2:
+            assert res[i]["status"] == rp.RP_EINVAL
+            assert np.array_equal(got, np.arange(n))
+        else:
+            want = np.arange(n, dtype=np.int32)
+            oracle.knuth_shuffle(want, Hs[i].cpu().numpy().view(np.uint64))
+            assert res[i]["status"] == 0
+            assert np.array_equal(got, want)
+
+
+def test_batch_structured_targets():
+    kinds = ["zero", "self", "prev", "hot4"]
+    n = 2000
+    Hs = [torch.from_numpy(workloads.adversarial_targets(n, k).view(np.int64)).to(DEV)
+          for k in kinds]
+    arrays = [torch.arange(n, dtype=torch.int32, device=DEV) for _ in kinds]
+    res = _run_batch(arrays, None, H=Hs)
+    for i, k in enumerate(kinds):
+        want = np.arange(n, dtype=np.int32)
+        oracle.knuth_shuffle(want, workloads.adversarial_targets(n, k))
+        assert res[i]["status"] == 0
+        assert np.array_equal(arrays[i].cpu().numpy(), want), k
+
+
+def test_autotune_then_batch():
+    sizes = workloads.batch_sizes(256, 8, 16, 3)
+    arrays = [torch.arange(int(n), dtype=torch.int32, device=DEV) for n in sizes]
+    seeds = [1000 + i for i in range(len(sizes))]
+    sched = rp.rp_batch_autotune(arrays, seeds=seeds, eps=0.5)
+    assert sched["workgroups_per_cu"] >= 1 and sched["table_ratio_x16"] >= 1
+    # the tuner ran on scratch copies: the arrays are untouched
+    assert all(torch.equal(a, torch.arange(a.numel(), dtype=torch.int32, device=DEV))
+               for a in arrays)
+    res = _run_batch(arrays, seeds)
+    for i in range(0, len(sizes), 17):
+        assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(sizes[i]), seeds[i]))
+    assert all(r["status"] == 0 for r in res)
+
+
+def test_config_4096_log_uniform_2p8_2p20():
+    sizes = workloads.batch_sizes(4096, 8, 20, 12345)
+    seeds = [1000 + i for i in range(len(sizes))]
+    arrays = [torch.arange(int(n), dtype=torch.int32, device=DEV) for n in sizes]
+    res = _run_batch(arrays, seeds)
+    assert all(r["status"] == 0 for r in res)
+    for i in range(len(sizes)):
+        assert res[i]["aux_words"] <= rp.rp_aux_bound_words(int(sizes[i]), 0.5)
+    # every result is a permutation
+    for a in arrays:
+        seen = torch.zeros(a.numel(), dtype=torch.bool, device=DEV)
+        seen[a.long()] = True
+        assert bool(seen.all())
+    # and a spread of them, including the largest, equals the oracle exactly
+    check = sorted(set(list(range(0, 4096, 97)) + [int(np.argmax(sizes))]))
+    for i in check:
+        assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(sizes[i]), seeds[i])), i
