@@ -10,6 +10,18 @@ so consecutive steps shuffle the same array again (seed = 1 + step).
 Prints one JSON line (see the "metric"/"roofline"/"cpu_baseline" fields).
 The first warm-up step runs on the identity array and is checked against the
 CPU oracle (sampled positions, exact) and for being a permutation.
+
+`--workload serve` replays Poisson arrival traces (exponential gaps, seed 7)
+at each rate for --duration seconds, n = floor(2^U) with U ~ Uniform[10, 26)
+from a SplitMix64 stream (seed 7), int64 A[i] = i, request seed 10^6 + id,
+eps = 0.5, through a server with a 64 GiB arena, once batched and once with
+one plain launch per request; it reports elements/s and p50/p99 latency.
+
+`--workload batch` measures the batched form instead: 4096 independent
+shuffles, n = floor(2^U) with U ~ Uniform[8, 20) drawn from a SplitMix64
+stream (seed 12345), int32 A[i] = i, instance seed 1000 + id, eps = 0.5, as
+one persistent launch per step under the autotuned schedule, beside one plain
+launch per instance over the same arrays.
 """
 from __future__ import annotations
 
@@ -25,29 +37,35 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 WORKLOAD = {"n": 1 << 30, "elem_bytes": 8, "eps": 0.5, "seed": 1}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rp_rounds_kernel_n2p30_int64_eps0.5_traffic.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2103_01216_amd", "csrc", f)
-               for f in ("rp.hip", "rp_device.h")]
+BATCH = {"count": 4096, "lo_log2": 8, "hi_log2": 20, "size_seed": 12345,
+         "seed_base": 1000, "eps": 0.5}
+CSRC = os.path.join(ROOT, "paper_2103_01216_amd", "csrc")
+TRAFFIC = {
+    "plain": (os.path.join(ROOT, "profiles", "rp_rounds_kernel_n2p30_int64_eps0.5_traffic.json"),
+              [os.path.join(CSRC, f) for f in ("rp.hip", "rp_device.h")]),
+    "batch": (os.path.join(ROOT, "profiles", "rp_batch_kernel_4096_loguniform_int32_traffic.json"),
+              [os.path.join(CSRC, f) for f in ("rp_batch.hip", "rp_device.h")]),
+}
 
 
-def _src_hash() -> str:
-    """sha256[:16] over the sources the shuffle kernel is compiled from."""
+def _src_hash(workload: str = "plain") -> str:
+    """sha256[:16] over the sources the workload's kernel is compiled from."""
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in TRAFFIC[workload][1]:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def _traffic_bytes():
+def _traffic_bytes(workload: str = "plain"):
     """Measured HBM bytes per launch from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC[workload][0]) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256_16") != _src_hash():
+    if rec.get("kernel_source_sha256_16") != _src_hash(workload):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -73,8 +91,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("plain", "batch", "serve"), default="plain")
+    ap.add_argument("--duration", type=float, default=60.0,
+                    help="serve workload: seconds of arrivals per rate")
+    ap.add_argument("--rates", default="50,200,1000",
+                    help="serve workload: arrival rates (requests/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch workload: skip the one-launch-per-instance comparison")
+    ap.add_argument("--schedule", default=None,
+                    help="batch workload: CUTOFF,RATIO16,WPC instead of autotuning")
     args = ap.parse_args()
 
     def log(msg):
@@ -82,11 +109,19 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not "
-              "supported by this build (the single-GPU kernel is the whole "
-              "path; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "supported: the single-GPU kernel is the whole path, and a "
+              "sharded form is not implemented", file=sys.stderr)
         sys.exit(2)
-    warmup = max(1, args.warmup)
+    if args.workload == "batch":
+        run_batch(args, log)
+    elif args.workload == "serve":
+        run_serve(args, log)
+    else:
+        run_plain(args, log)
 
+
+def run_plain(args, log):
+    warmup = max(1, args.warmup)
     import numpy as np
     import torch
     import paper_2103_01216_amd as rp
@@ -178,6 +213,276 @@ def main():
         del A
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(log)
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args, log):
+    """The batched form on the 4096-instance workload (see module docstring)."""
+    warmup = max(1, args.warmup)
+    import numpy as np
+    import torch
+    import paper_2103_01216_amd as rp
+    from paper_2103_01216_amd import workloads
+
+    count, eps = BATCH["count"], BATCH["eps"]
+    sizes = workloads.batch_sizes(count, BATCH["lo_log2"], BATCH["hi_log2"], BATCH["size_seed"])
+    seeds = [BATCH["seed_base"] + i for i in range(count)]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    total = int(offs[-1])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    # One allocation; request i is the view [offs[i], offs[i+1]).
+    seg_start = torch.repeat_interleave(torch.from_numpy(offs[:-1]).to(dev),
+                                        torch.from_numpy(sizes).to(dev))
+    ident = (torch.arange(total, dtype=torch.int64, device=dev) - seg_start).to(torch.int32)
+    big = ident.clone()
+    arrays = [big[int(offs[i]):int(offs[i + 1])] for i in range(count)]
+    torch.cuda.synchronize()
+    log(f"batch: {count} instances, {total} int32 elements "
+        f"(n from {sizes.min()} to {sizes.max()})")
+
+    if args.schedule:
+        c, r16, w = (int(x) for x in args.schedule.split(","))
+        sched = {"wave_cutoff": c, "table_ratio_x16": r16, "workgroups_per_cu": w,
+                 "tuned_ms_x1000": 0}
+        log(f"schedule given: {sched}")
+    else:
+        t0 = time.perf_counter()
+        sched = rp.rp_batch_autotune(arrays, seeds=seeds, eps=eps, stream=stream)
+        log(f"autotune: {sched} in {time.perf_counter() - t0:.1f} s")
+    reqs = rp.rp_batch_requests(arrays, seeds=seeds, eps=eps)
+
+    parity = {"checked": False}
+    results = None
+    for w in range(warmup):
+        if w == 0:
+            big.copy_(ident)
+        b = rp.rp_batch_submit(arrays, requests=reqs, stream=stream, schedule=sched)
+        results = b.results()
+        b.release()
+        if w == 0 and not args.no_check:
+            import oracle
+            seen = torch.zeros(total, dtype=torch.bool, device=dev)
+            seen[seg_start + big.long()] = True
+            perm_ok = bool(seen.all())
+            del seen
+            pick = sorted(set(list(range(0, count, 97)) + [int(np.argmax(sizes))]))
+            exact = True
+            for i in pick:
+                want = np.arange(int(sizes[i]), dtype=np.int32)
+                oracle.knuth_shuffle_seed(want, seeds[i])
+                exact = exact and bool(np.array_equal(arrays[i].cpu().numpy(), want))
+            status_ok = all(r["status"] == 0 for r in results)
+            aux_ok = all(r["aux_words"] <= rp.rp_aux_bound_words(int(n), eps)
+                         for r, n in zip(results, sizes))
+            log(f"parity: permutation={perm_ok} exact={exact} ({len(pick)} instances) "
+                f"status_ok={status_ok} aux_within_bound={aux_ok}")
+            parity = {"checked": True, "all_permutations": perm_ok,
+                      "instances_exact_vs_oracle": len(pick), "exact": exact,
+                      "aux_within_bound": aux_ok}
+            if not (perm_ok and exact and status_ok and aux_ok):
+                log("PARITY FAILURE")
+                sys.exit(1)
+            first = big.clone()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        b = rp.rp_batch_submit(arrays, requests=reqs, stream=stream, schedule=sched)
+        ev[i][1].record(stream)
+        b.results()
+        b.release()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    step_ms = [a.elapsed_time(c) for a, c in ev]
+    ms = sum(step_ms) / len(step_ms)
+    value = total * args.steps / wall
+    log(f"batch steps ms: {', '.join(f'{x:.2f}' for x in step_ms)}; wall {wall:.3f} s")
+
+    plain = None
+    if not args.no_plain:
+        # Same arrays, one rp_shuffle_inplace launch per instance, identity input.
+        big.copy_(ident)
+        for i in range(8):
+            rp.rp_shuffle_inplace(arrays[i], seed=seeds[i], eps=eps, stream=stream, stats=False)
+        big.copy_(ident)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(count):
+            rp.rp_shuffle_inplace(arrays[i], seed=seeds[i], eps=eps, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        same = bool(torch.equal(big, first)) if parity["checked"] else None
+        log(f"plain per-instance launches: {pw:.3f} s; equal to the batched result: {same}")
+        plain = {"value": total / pw, "unit": "elements/s", "wall_s": pw,
+                 "launches": count, "equal_to_batched_result": same}
+
+    alg_bytes = 4 * 4 * total                    # A[s], A[H[s]]: read + write, int32
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "batched in-place shuffle elements/s (4096 instances, one launch) "
+                  "vs one plain launch per instance",
+        "value": value,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batched: 4096 shuffles, n=floor(2^U), U~Uniform[8,20) "
+                               "from SplitMix64 stream seed 12345, int32 A[i]=i, "
+                               "seed 1000+id, eps=0.5",
+                   "instances": count, "total_elements": total,
+                   "schedule": sched,
+                   "rounds_total": sum(r["rounds"] for r in results),
+                   "plain_per_instance": plain,
+                   "speedup_vs_plain": (value / plain["value"]) if plain else None},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": _traffic_bytes("batch"),
+                     "kernel": "rp_batch_kernel", "kernel_ms_events": ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "parity": parity,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = list(range(0, count, 4))
+        hosts = [np.arange(int(sizes[i]), dtype=np.int32) for i in sample]
+        t0 = time.perf_counter()
+        for a, i in zip(hosts, sample):
+            oracle.knuth_shuffle_seed(a, seeds[i])
+        dt = time.perf_counter() - t0
+        n_s = int(sum(int(sizes[i]) for i in sample))
+        log(f"cpu oracle: {len(sample)} instances, {n_s} elements in {dt:.2f} s")
+        out["cpu_baseline"] = {"value": n_s / dt, "unit": "elements/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"every 4th instance of the batch ({len(sample)} "
+                                         f"shuffles, {n_s} int32 elements), sequential "
+                                         "Knuth shuffle on one host core"}
+    print(json.dumps(out), flush=True)
+
+
+SERVE = {"lo_log2": 10, "hi_log2": 26, "size_seed": 7, "arrival_seed": 7,
+         "seed_base": 10**6, "eps": 0.5, "budget": 64 << 30, "elem_bytes": 8}
+
+
+def _replay(rp, mode, arrivals, sizes, seeds, log, drain_s):
+    """Submit each request at its arrival time; collect completion times.
+    Returns (latencies_s, completed_elements, span_s, unfinished)."""
+    import threading
+    srv = rp.Server(SERVE["budget"], mode=mode, auto_release=True)
+    tickets = {}
+    lat = {}
+    stop = threading.Event()
+
+    def collect():
+        while not stop.is_set() or len(lat) < len(tickets):
+            for t in srv.completed():
+                info = srv.info(t)
+                lat[t] = (info["t_done_ns"] - info["t_submit_ns"]) * 1e-9, info
+                srv.release(t)
+            if stop.is_set() and len(lat) >= len(tickets):
+                break
+            time.sleep(0.0005)
+            if stop.is_set() and time.perf_counter() > deadline[0]:
+                break
+
+    deadline = [float("inf")]
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (ta, n) in enumerate(zip(arrivals, sizes)):
+        wait = t0 + ta - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets[srv.submit(int(n), SERVE["elem_bytes"], seeds[i], SERVE["eps"])] = i
+    t_submitted = time.perf_counter()
+    deadline[0] = t_submitted + drain_s
+    stop.set()
+    th.join()
+    t_end = time.perf_counter()
+    done = dict(lat)
+    unfinished = len(tickets) - len(done)
+    st = srv.stats()
+    if unfinished:
+        log(f"  {unfinished} requests unfinished {drain_s:.0f} s after the last arrival; "
+            "their latency is counted as at least the time they waited")
+    now_ns = time.monotonic_ns()
+    lats = []
+    t_first = min(i["t_submit_ns"] for _, i in done.values()) if done else 0
+    t_last = max(i["t_done_ns"] for _, i in done.values()) if done else 0
+    for t in tickets:
+        if t in done:
+            lats.append(done[t][0])
+        else:
+            lats.append((now_ns - srv.info(t)["t_submit_ns"]) * 1e-9)
+    elems = sum(int(sizes[tickets[t]]) for t in done)
+    srv.close()
+    span = max((t_last - t_first) * 1e-9, 1e-9)
+    return lats, elems, span, unfinished, st
+
+
+def run_serve(args, log):
+    """The serving form on Poisson arrival traces (see module docstring)."""
+    import numpy as np
+    import torch
+    import paper_2103_01216_amd as rp
+    from paper_2103_01216_amd import workloads
+
+    torch.cuda.set_device(0)
+    torch.zeros(1, device="cuda:0")
+    rates = [float(r) for r in args.rates.split(",")]
+    per_rate = {}
+    for lam in rates:
+        count = int(lam * args.duration)
+        gaps = np.random.default_rng(SERVE["arrival_seed"]).exponential(1.0 / lam, size=count)
+        arrivals = np.cumsum(gaps)
+        sizes = workloads.batch_sizes(count, SERVE["lo_log2"], SERVE["hi_log2"],
+                                      SERVE["size_seed"])
+        seeds = [SERVE["seed_base"] + i for i in range(count)]
+        offered = float(sizes.sum()) / float(arrivals[-1])
+        rec = {"requests": count, "offered_elements_per_s": offered}
+        for name, mode in (("batched", rp.RP_SERVE_BATCHED), ("plain", rp.RP_SERVE_PLAIN)):
+            log(f"rate {lam:g}/s, {name}: {count} requests, offered {offered:.3g} elements/s")
+            lats, elems, span, unfinished, st = _replay(rp, mode, arrivals, sizes, seeds, log,
+                                                        drain_s=max(30.0, args.duration / 2))
+            lat_ms = np.array(lats) * 1e3
+            rec[name] = {"elements_per_s": elems / span,
+                         "p50_ms": float(np.percentile(lat_ms, 50)),
+                         "p99_ms": float(np.percentile(lat_ms, 99)),
+                         "completed": count - unfinished, "unfinished": unfinished,
+                         "launches": st["launches"], "peak_bytes": st["peak_bytes"]}
+            log(f"  {name}: {elems / span:.3g} elements/s, p50 {rec[name]['p50_ms']:.2f} ms, "
+                f"p99 {rec[name]['p99_ms']:.2f} ms, launches {st['launches']}")
+        per_rate[f"{lam:g}"] = rec
+    top = per_rate[f"{rates[-1]:g}"]
+    out = {
+        "metric": "served shuffle elements/s with p50/p99 latency (Poisson arrivals)",
+        "value": top["batched"]["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": len(rates),
+        "warmup": 0,
+        "ms_per_step": args.duration * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals (seed 7), n=floor(2^U), "
+                               "U~Uniform[10,26) from SplitMix64 stream seed 7, int64 "
+                               "A[i]=i, seed 1e6+id, eps=0.5, 64 GiB arena",
+                   "duration_s": args.duration, "rates": per_rate,
+                   "value_is": f"batched elements/s at {rates[-1]:g} requests/s"},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -47,6 +47,7 @@ extern "C" {
 #define RP_EDEVICE (-3) /* a HIP runtime call failed */
 #define RP_ETIMEOUT (-4) /* device watchdog fired (a barrier or the round count
                             exceeded its bound); reported through stats */
+#define RP_ECANCELED (-5) /* rp_server_destroy: the request was never launched */
 
 /*
  * Per-call statistics, written by the device and copied into caller memory
@@ -142,12 +143,12 @@ int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
  * Each request is an independent call of the operation above on its own array
  * (same semantics and the same auxiliary bound per request, floor(n^(1-eps))
  * words, here held in the on-chip LDS of the lanes that run it).  Requests of
- * one batch share one record size; n < 2^24 per request.  The batch is
+ * one batch share one record size; n < 2^32 per request.  The batch is
  * stream-ordered; completion can be observed without blocking.
  */
 typedef struct rp_batch_request {
     void *A;                 /* device records, permuted in place (caller-owned) */
-    uint64_t n;              /* number of records, < 2^24 */
+    uint64_t n;              /* number of records, < 2^32 */
     uint32_t elem_bytes;     /* multiple of 4 in [4, 256]; equal for the batch */
     uint32_t reserved;       /* 0 */
     const uint64_t *H;       /* device targets (H[i] <= i) or NULL: seed mode */
@@ -210,6 +211,116 @@ int rp_batch_results(uint64_t batch_id, rp_batch_result *out);
 
 /* Waits for the batch and frees its bookkeeping; the id becomes invalid. */
 int rp_batch_release(uint64_t batch_id);
+
+/* ------------------------------------------------------------------------
+ * Serving form: a request loop on one device.
+ *
+ * The paper motivates in-place algorithms by the limited memory of a single
+ * machine (Section 1) and reports the memory each algorithm holds beyond its
+ * input (Section 7.6).  A server applies that to a stream of shuffle
+ * requests: it owns a device arena of a fixed budget, admits requests in
+ * arrival order while their arrays fit in the free part of the arena, fills
+ * each admitted array on the device, and runs admitted requests as batched
+ * launches (the batched form above) that overlap on the device with launches
+ * still running.  Each request's result is the Knuth shuffle of its array
+ * with its seed, whatever else runs beside it.  One host thread per server
+ * does all device work; the calls below only exchange bookkeeping with it and
+ * never block on the GPU (rp_server_destroy excepted).
+ * ------------------------------------------------------------------------ */
+
+#define RP_SERVE_BATCHED 0  /* admitted requests go out as batched launches */
+#define RP_SERVE_PLAIN 1    /* one rp_shuffle_inplace per request, in order */
+
+#define RP_INIT_IDENTITY 0  /* A[i] = i (elem_bytes 4 or 8: the integer i;
+                               other sizes: word 0 = i, other words 0) */
+#define RP_INIT_COPY 1      /* A = n * elem_bytes bytes copied from src
+                               (device or pinned host memory) */
+
+#define RP_REQ_QUEUED 0     /* waiting for arena space */
+#define RP_REQ_ADMITTED 1   /* array allocated, not launched yet */
+#define RP_REQ_RUNNING 2    /* launched */
+#define RP_REQ_DONE 3       /* finished; A holds the result until released */
+
+typedef struct rp_server_config {
+    uint64_t mem_budget_bytes;   /* arena size: bound on the bytes of all
+                                    admitted, unreleased arrays */
+    uint32_t mode;               /* RP_SERVE_BATCHED or RP_SERVE_PLAIN */
+    uint32_t max_batch;          /* requests per launch; 0: no limit */
+    uint32_t large_log2;         /* n >= 2^large_log2 uses the large-request
+                                    streams; 0: 22 */
+    uint32_t tick_us;            /* dispatcher poll interval; 0: 50 */
+    uint32_t auto_release;       /* 1: free each array as soon as it is done
+                                    (results are not kept) */
+    uint32_t reserved;           /* 0 */
+    rp_batch_schedule schedule;  /* all zero: the tuned or default schedule */
+} rp_server_config;
+
+typedef struct rp_server_request {
+    uint64_t n;                  /* records, 1 <= n < 2^32 */
+    uint32_t elem_bytes;         /* multiple of 4 in [4, 256] */
+    uint32_t init;               /* RP_INIT_IDENTITY or RP_INIT_COPY */
+    const void *src;             /* RP_INIT_COPY: source records; the caller
+                                    keeps them valid until the request runs */
+    uint64_t seed;               /* H[i] = splitmix64(seed ^ i) mod (i+1) */
+    double eps;                  /* in (0, 1) */
+} rp_server_request;
+
+typedef struct rp_server_ticket_info {
+    int32_t state;               /* RP_REQ_* */
+    int32_t status;              /* RP_OK, or the request's error once done */
+    uint64_t t_submit_ns;        /* steady-clock times (ns) of each step; */
+    uint64_t t_admit_ns;         /* 0 when not reached yet */
+    uint64_t t_launch_ns;
+    uint64_t t_done_ns;          /* when the dispatcher saw completion */
+    void *A;                     /* device array (NULL until admitted, and
+                                    after release) */
+    uint64_t rounds;             /* rounds run (batched mode) */
+    uint32_t aux_words;          /* round-state words used */
+    uint32_t reserved;
+} rp_server_ticket_info;
+
+typedef struct rp_server_stats {
+    uint64_t submitted, admitted, done, launches;
+    uint64_t bytes_in_use;       /* arena bytes held by admitted requests */
+    uint64_t peak_bytes;         /* maximum of bytes_in_use so far */
+    uint64_t elements_done;      /* sum of n over finished requests */
+} rp_server_stats;
+
+/* Create a server on the current device: allocates the arena and starts the
+ * dispatcher thread.  *server (host) receives its handle.  RP_EINVAL for a bad
+ * config, RP_ENOMEM when the arena cannot be allocated. */
+int rp_server_create(const rp_server_config *cfg, uint64_t *server);
+
+/* Queue a request (host struct, copied).  Never blocks.  RP_EINVAL for a bad
+ * request or one larger than the whole budget.  *ticket (host) identifies it. */
+int rp_server_submit(uint64_t server, const rp_server_request *req, uint64_t *ticket);
+
+/* Snapshot of a request's state (host struct).  RP_EINVAL for an unknown or
+ * released ticket. */
+int rp_server_info(uint64_t server, uint64_t ticket, rp_server_ticket_info *info);
+
+/* Tickets finished since the last call, oldest first: up to max of them are
+ * written to tickets (host) and *count (host) says how many. */
+int rp_server_completed(uint64_t server, uint64_t *tickets, uint32_t max, uint32_t *count);
+
+/* Enqueue, on `stream`, a copy of a finished request's n * elem_bytes result
+ * bytes to dst (device or pinned host memory, caller-owned).  RP_PENDING if
+ * the request has not finished; RP_EINVAL for an unknown ticket or one whose
+ * array was already freed (auto_release).  Release the ticket only after the
+ * copy has completed on `stream`. */
+int rp_server_copy_out(uint64_t server, uint64_t ticket, void *dst, void *stream);
+
+/* Free a finished request's array (its space returns to the arena) and forget
+ * the ticket.  RP_PENDING if the request has not finished yet. */
+int rp_server_release(uint64_t server, uint64_t ticket);
+
+/* Counters (host struct). */
+int rp_server_stats_get(uint64_t server, rp_server_stats *out);
+
+/* Stop accepting requests, let running ones finish, cancel the ones not yet
+ * launched (status RP_ECANCELED), free all memory and end the dispatcher
+ * thread.  Blocks until done. */
+int rp_server_destroy(uint64_t server);
 
 #ifdef __cplusplus
 }

@@ -24,9 +24,11 @@ RP_EINVAL = -1
 RP_ENOMEM = -2
 RP_EDEVICE = -3
 RP_ETIMEOUT = -4
+RP_ECANCELED = -5
 
 _ERRORS = {RP_EINVAL: "RP_EINVAL", RP_ENOMEM: "RP_ENOMEM",
-           RP_EDEVICE: "RP_EDEVICE", RP_ETIMEOUT: "RP_ETIMEOUT"}
+           RP_EDEVICE: "RP_EDEVICE", RP_ETIMEOUT: "RP_ETIMEOUT",
+           RP_ECANCELED: "RP_ECANCELED"}
 
 STATS_FIELDS = ("k", "aux_words", "aux_bound_words", "rounds", "attempts",
                 "retries", "max_active", "self_loops", "grid",
@@ -272,18 +274,31 @@ class Batch:
                 raise RpError(rc, "rp_batch_release")
 
 
+def rp_batch_requests(arrays, *, seeds=None, H=None, eps: float = 0.5):
+    """Marshal the request descriptors once, for repeated submits of the same
+    arrays (pass the result as `requests=` to rp_batch_submit)."""
+    return _requests(arrays, seeds, H, eps)
+
+
 def rp_batch_submit(arrays, *, seeds=None, H=None, eps: float = 0.5,
-                    schedule: dict | None = None, stream=None) -> Batch:
+                    schedule: dict | None = None, stream=None, requests=None) -> Batch:
     """Enqueue one shuffle per tensor in `arrays` as a single persistent launch.
 
     seeds: per-request seeds (seed mode) or None with H: per-request device
     target tensors.  schedule: dict with wave_cutoff, table_ratio_x16,
-    workgroups_per_cu, or None for the tuned/default schedule.
+    workgroups_per_cu, or None for the tuned/default schedule.  requests:
+    descriptors from rp_batch_requests for these same arrays (then seeds, H
+    and eps are taken from it).
     """
     import torch
     if stream is None:
         stream = torch.cuda.current_stream()
-    reqs = _requests(arrays, seeds, H, eps)
+    if requests is not None:
+        if len(requests) != len(arrays):
+            raise ValueError("requests were built for a different batch")
+        reqs = requests
+    else:
+        reqs = _requests(arrays, seeds, H, eps)
     sched = None
     if schedule is not None:
         sched = rp_batch_schedule(schedule["wave_cutoff"], schedule["table_ratio_x16"],
@@ -309,3 +324,156 @@ def rp_batch_autotune(arrays, *, seeds=None, eps: float = 0.5, stream=None) -> d
     if rc != RP_OK:
         raise RpError(rc, "rp_batch_autotune")
     return _schedule_dict(out)
+
+
+# ------------------------------------------------------------------ serving
+
+RP_SERVE_BATCHED = 0
+RP_SERVE_PLAIN = 1
+RP_INIT_IDENTITY = 0
+RP_INIT_COPY = 1
+RP_REQ_QUEUED, RP_REQ_ADMITTED, RP_REQ_RUNNING, RP_REQ_DONE = 0, 1, 2, 3
+
+
+class rp_server_config(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("mode", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("large_log2", ctypes.c_uint32),
+                ("tick_us", ctypes.c_uint32), ("auto_release", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("schedule", rp_batch_schedule)]
+
+
+class rp_server_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("elem_bytes", ctypes.c_uint32),
+                ("init", ctypes.c_uint32), ("src", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("eps", ctypes.c_double)]
+
+
+class rp_server_ticket_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("A", ctypes.c_void_p), ("rounds", ctypes.c_uint64),
+                ("aux_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class rp_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("submitted", "admitted", "done", "launches", "bytes_in_use",
+                 "peak_bytes", "elements_done")]
+
+
+def _server_lib():
+    L = _batch_lib()
+    if not getattr(L, "_server_ready", False):
+        u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        P = ctypes.POINTER
+        for name, args in (
+                ("rp_server_create", [P(rp_server_config), P(u64)]),
+                ("rp_server_submit", [u64, P(rp_server_request), P(u64)]),
+                ("rp_server_info", [u64, u64, P(rp_server_ticket_info)]),
+                ("rp_server_completed", [u64, P(u64), u32, P(u32)]),
+                ("rp_server_release", [u64, u64]),
+                ("rp_server_copy_out", [u64, u64, ctypes.c_void_p, ctypes.c_void_p]),
+                ("rp_server_stats_get", [u64, P(rp_server_stats)]),
+                ("rp_server_destroy", [u64])):
+            fn = getattr(L, name)
+            fn.restype = i32
+            fn.argtypes = args
+        L._server_ready = True
+    return L
+
+
+class Server:
+    """A request loop on the current device (rp_server_* of include/rp.h)."""
+
+    def __init__(self, mem_budget_bytes: int, *, mode: int = RP_SERVE_BATCHED,
+                 max_batch: int = 0, large_log2: int = 0, tick_us: int = 0,
+                 auto_release: bool = False, schedule: dict | None = None):
+        cfg = rp_server_config()
+        cfg.mem_budget_bytes = int(mem_budget_bytes)
+        cfg.mode = mode
+        cfg.max_batch = max_batch
+        cfg.large_log2 = large_log2
+        cfg.tick_us = tick_us
+        cfg.auto_release = 1 if auto_release else 0
+        if schedule:
+            cfg.schedule = rp_batch_schedule(schedule["wave_cutoff"],
+                                             schedule["table_ratio_x16"],
+                                             schedule["workgroups_per_cu"], 0)
+        h = ctypes.c_uint64(0)
+        rc = _server_lib().rp_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != RP_OK:
+            raise RpError(rc, "rp_server_create")
+        self.handle = int(h.value)
+        self._closed = False
+
+    def submit(self, n: int, elem_bytes: int, seed: int, eps: float = 0.5,
+               src=None) -> int:
+        """Queue one request; src (optional) is a tensor whose bytes are copied
+        in (it must stay alive until the request has run)."""
+        q = rp_server_request()
+        q.n = int(n)
+        q.elem_bytes = int(elem_bytes)
+        q.init = RP_INIT_IDENTITY if src is None else RP_INIT_COPY
+        q.src = None if src is None else src.data_ptr()
+        q.seed = int(seed) & (2**64 - 1)
+        q.eps = float(eps)
+        t = ctypes.c_uint64(0)
+        rc = _server_lib().rp_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t))
+        if rc != RP_OK:
+            raise RpError(rc, "rp_server_submit")
+        return int(t.value)
+
+    def info(self, ticket: int) -> dict:
+        out = rp_server_ticket_info()
+        rc = _server_lib().rp_server_info(self.handle, ticket, ctypes.byref(out))
+        if rc != RP_OK:
+            raise RpError(rc, "rp_server_info")
+        return {f: getattr(out, f) for f, _ in rp_server_ticket_info._fields_
+                if f != "reserved"}
+
+    def completed(self, max_count: int = 4096) -> list:
+        buf = (ctypes.c_uint64 * max_count)()
+        c = ctypes.c_uint32(0)
+        rc = _server_lib().rp_server_completed(self.handle, buf, max_count, ctypes.byref(c))
+        if rc != RP_OK:
+            raise RpError(rc, "rp_server_completed")
+        return [int(buf[i]) for i in range(c.value)]
+
+    def copy_out(self, ticket: int, dst, stream=None):
+        """Enqueue a copy of a finished request's array into tensor dst (at
+        least n * elem_bytes bytes) on `stream` (default: the current one)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        rc = _server_lib().rp_server_copy_out(self.handle, ticket, dst.data_ptr(),
+                                              ctypes.c_void_p(stream.cuda_stream))
+        if rc != RP_OK:
+            raise RpError(rc, "rp_server_copy_out")
+
+    def release(self, ticket: int) -> bool:
+        """True when released, False while the request is still running."""
+        rc = _server_lib().rp_server_release(self.handle, ticket)
+        if rc not in (RP_OK, RP_PENDING):
+            raise RpError(rc, "rp_server_release")
+        return rc == RP_OK
+
+    def stats(self) -> dict:
+        out = rp_server_stats()
+        rc = _server_lib().rp_server_stats_get(self.handle, ctypes.byref(out))
+        if rc != RP_OK:
+            raise RpError(rc, "rp_server_stats_get")
+        return {f: int(getattr(out, f)) for f, _ in rp_server_stats._fields_}
+
+    def close(self):
+        if not self._closed:
+            self._closed = True
+            rc = _server_lib().rp_server_destroy(self.handle)
+            if rc != RP_OK:
+                raise RpError(rc, "rp_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -48,7 +48,14 @@ constexpr int BWAVES = BWG / 64;
 constexpr int BM = 8;                    // swap slots per lane (maximum)
 constexpr uint32_t LDS_WORDS = 8192;     // 32 KB of round state per workgroup
 constexpr uint32_t WAVE_WORDS = LDS_WORDS / BWAVES;
-constexpr uint32_t BATCH_MAX_N = 1u << 24;  // ranks fit 24 bits without a throttle
+// Priorities hold the rank s - cnew in 24 bits.  A swap that enters the
+// window stays active at most k rounds (every round the highest active swap
+// commits, and no swap above it ever enters again), and the window moves down
+// by at most k per round, so ranks stay below k*k + k: within 24 bits for any
+// n once k <= 4095, with no rank throttle.
+constexpr uint32_t K_MAX_WG = BWG * BM;  // largest k of any request
+static_assert((uint64_t)K_MAX_WG * K_MAX_WG + K_MAX_WG < (1ull << RANKB), "ranks overflow");
+constexpr uint64_t BATCH_MAX_N = 1ull << 32;  // indices are 32-bit
 
 struct BatchReq {
     unsigned char *A;
@@ -437,13 +444,79 @@ int env_or(const char *name, int dflt)
     return v && *v ? atoi(v) : dflt;
 }
 
+// Pinned host buffers of one batch.  Allocating pinned memory costs far more
+// than a small batch's kernel, so released buffers go back to a pool.
+struct HostBufs {
+    BatchReq *staging = nullptr;    // pinned copy of the descriptors
+    rp_batch_result *res = nullptr; // host-visible results
+    uint32_t *done = nullptr;       // coherent: [1..cap] completion flags
+    uint32_t cap = 0;
+};
+
+std::mutex g_pool_mu;
+std::vector<HostBufs> g_pool;
+constexpr size_t POOL_MAX = 16;
+
+void free_host(HostBufs &h)
+{
+    if (h.staging)
+        (void)hipHostFree(h.staging);
+    if (h.res)
+        (void)hipHostFree(h.res);
+    if (h.done)
+        (void)hipHostFree(h.done);
+    h = HostBufs{};
+}
+
+bool acquire_host(uint32_t count, HostBufs *out)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        size_t best = g_pool.size();
+        for (size_t i = 0; i < g_pool.size(); i++)
+            if (g_pool[i].cap >= count && (best == g_pool.size() || g_pool[i].cap < g_pool[best].cap))
+                best = i;
+        if (best < g_pool.size()) {
+            *out = g_pool[best];
+            g_pool.erase(g_pool.begin() + (long)best);
+            return true;
+        }
+    }
+    HostBufs h;
+    h.cap = std::max(count, 64u);
+    if (hipHostMalloc(reinterpret_cast<void **>(&h.staging), sizeof(BatchReq) * h.cap) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&h.res), sizeof(rp_batch_result) * h.cap) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&h.done), sizeof(uint32_t) * (h.cap + 1),
+                      hipHostMallocCoherent) != hipSuccess) {
+        free_host(h);
+        return false;
+    }
+    *out = h;
+    return true;
+}
+
+// Only after the stream has passed every use of the buffers.
+void return_host(HostBufs &h)
+{
+    if (!h.staging)
+        return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool.size() < POOL_MAX) {
+        g_pool.push_back(h);
+        h = HostBufs{};
+    } else {
+        free_host(h);
+    }
+}
+
 struct Batch {
     hipStream_t stream = nullptr;
     uint32_t count = 0;
     void *dev = nullptr;            // reqs | claims
-    rp_batch_result *res = nullptr; // host-visible (pinned)
-    uint32_t *done = nullptr;       // host-visible (pinned): [1..count] flags
-    BatchReq *staging = nullptr;    // pinned copy of the descriptors
+    HostBufs host;
+    rp_batch_result *res = nullptr; // = host.res
+    uint32_t *done = nullptr;       // = host.done
+    BatchReq *staging = nullptr;    // = host.staging
 };
 
 std::mutex g_bmu;
@@ -543,13 +616,11 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t a, uint32_t c) { return reqs[a].n > reqs[c].n; });
-    if (hipHostMalloc(reinterpret_cast<void **>(&b->staging),
-                      sizeof(BatchReq) * std::max(1u, count)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&b->res),
-                      sizeof(rp_batch_result) * std::max(1u, count)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&b->done),
-                      sizeof(uint32_t) * (count + 1), hipHostMallocCoherent) != hipSuccess)
+    if (!acquire_host(count, &b->host))
         return RP_ENOMEM;
+    b->staging = b->host.staging;
+    b->res = b->host.res;
+    b->done = b->host.done;
     std::memset(b->done, 0, sizeof(uint32_t) * (count + 1));
     std::memset(b->res, 0, sizeof(rp_batch_result) * std::max(1u, count));
     uint32_t n_wg = 0;
@@ -617,14 +688,14 @@ void release_batch(Batch &b)
 {
     if (b.dev)
         (void)hipFreeAsync(b.dev, b.stream);
-    if (b.staging || b.res || b.done)
-        (void)hipStreamSynchronize(b.stream);
-    if (b.staging)
-        (void)hipHostFree(b.staging);
-    if (b.res)
-        (void)hipHostFree(b.res);
-    if (b.done)
-        (void)hipHostFree(b.done);
+    if (b.host.staging) {
+        // The descriptors' copy and the kernel's result writes must be done
+        // before the buffers serve another batch.
+        if (hipStreamSynchronize(b.stream) == hipSuccess)
+            return_host(b.host);
+        else
+            free_host(b.host);
+    }
     b = Batch{};
 }
 
@@ -752,7 +823,7 @@ int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream
         q.A = static_cast<unsigned char *>(scratch) + off * eb;
         off += q.n;
     }
-    const uint32_t cutoffs[] = {1u << 10, 1u << 12, 1u << 14, 1u << 16, 1u << 18, BATCH_MAX_N};
+    const uint32_t cutoffs[] = {1u << 10, 1u << 12, 1u << 14, 1u << 16, 1u << 18, 0xFFFFFFFFu};
     const uint32_t ratios[] = {12, 16, 24};
     const uint32_t wpcs[] = {2, 4, 8};
     hipEvent_t e0, e1;

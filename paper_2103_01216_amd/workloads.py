@@ -91,7 +91,19 @@ def adversarial_targets(n: int, kind: str) -> np.ndarray:
     return h.astype(np.uint64)
 
 
+def splitmix64_stream(seed: int, count: int) -> np.ndarray:
+    """The first `count` outputs of the SplitMix64 generator whose state
+    starts at `seed` (state += golden gamma, then the output mix), uint64."""
+    state = (np.uint64(seed) + np.arange(1, count + 1, dtype=np.uint64) * np.uint64(GOLD))
+    with np.errstate(over="ignore"):
+        z = state
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(C1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(C2)
+        return z ^ (z >> np.uint64(31))
+
+
 def batch_sizes(count: int, lo_log2: float, hi_log2: float, seed: int) -> np.ndarray:
-    """Log-uniform sizes n = floor(2^U), U ~ Uniform[lo_log2, hi_log2)."""
-    rng = np.random.default_rng(seed)
-    return np.floor(2.0 ** rng.uniform(lo_log2, hi_log2, size=count)).astype(np.int64)
+    """Log-uniform sizes n = floor(2^U), U = lo + (hi - lo) * u with u the top
+    53 bits of the i-th SplitMix64 output (state starting at `seed`) / 2^53."""
+    u = (splitmix64_stream(seed, count) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u)).astype(np.int64)

@@ -147,3 +147,27 @@ def test_config_4096_log_uniform_2p8_2p20():
     check = sorted(set(list(range(0, 4096, 97)) + [int(np.argmax(sizes))]))
     for i in check:
         assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(sizes[i]), seeds[i])), i
+
+
+def test_large_request_in_a_batch():
+    """Requests far above the size of the rank field (2^24) run in workgroup
+    mode without a rank throttle; checked at sampled positions plus the
+    permutation property."""
+    sizes = [(1 << 25) + 7, 3000, (1 << 24) + 1, 70000]
+    seeds = [91, 92, 93, 94]
+    arrays = [torch.arange(n, dtype=torch.int32, device=DEV) for n in sizes]
+    res = _run_batch(arrays, seeds, schedule={"wave_cutoff": 1 << 12,
+                                              "table_ratio_x16": 16,
+                                              "workgroups_per_cu": 4})
+    for i, n in enumerate(sizes):
+        assert res[i]["status"] == 0
+        assert res[i]["aux_words"] <= rp.rp_aux_bound_words(n, 0.5)
+        a = arrays[i]
+        seen = torch.zeros(n, dtype=torch.bool, device=DEV)
+        seen[a.long()] = True
+        assert bool(seen.all())
+        rng = np.random.default_rng(i)
+        pos = np.unique(np.concatenate([[0, 1, n - 2, n - 1], rng.integers(0, n, 400)]))
+        want = oracle.sample_sources(n, pos, seed=seeds[i])
+        got = a[torch.from_numpy(pos.astype(np.int64)).to(DEV)].cpu().numpy()
+        assert np.array_equal(got.astype(np.uint64), want.astype(np.uint64)), (i, n)
