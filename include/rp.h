@@ -167,12 +167,17 @@ typedef struct rp_batch_result {
 /* Schedule of a batch launch (chosen by rp_batch_autotune, or defaults):
  * requests with n >= wave_cutoff run one per workgroup, smaller ones one per
  * wave; table_ratio_x16 = 16 * reservation slots per active swap;
- * workgroups_per_cu = resident workgroups per compute unit. */
+ * workgroups_per_cu = resident workgroups per compute unit (at most what the
+ * workgroup size allows); workgroup_lanes = 256 or 1024 (0: 256) -- a
+ * 1024-lane workgroup holds four times as many active swaps of one request,
+ * so a large request needs a quarter of the rounds. */
 typedef struct rp_batch_schedule {
     uint32_t wave_cutoff;
     uint32_t table_ratio_x16;
     uint32_t workgroups_per_cu;
     uint32_t tuned_ms_x1000;  /* out: best trial time in microseconds */
+    uint32_t workgroup_lanes;
+    uint32_t reserved;        /* 0 */
 } rp_batch_schedule;
 
 /*

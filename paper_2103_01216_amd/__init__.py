@@ -186,7 +186,14 @@ class rp_batch_result(ctypes.Structure):
 
 class rp_batch_schedule(ctypes.Structure):
     _fields_ = [("wave_cutoff", ctypes.c_uint32), ("table_ratio_x16", ctypes.c_uint32),
-                ("workgroups_per_cu", ctypes.c_uint32), ("tuned_ms_x1000", ctypes.c_uint32)]
+                ("workgroups_per_cu", ctypes.c_uint32), ("tuned_ms_x1000", ctypes.c_uint32),
+                ("workgroup_lanes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def _schedule_struct(d: dict) -> rp_batch_schedule:
+    return rp_batch_schedule(int(d["wave_cutoff"]), int(d["table_ratio_x16"]),
+                             int(d["workgroups_per_cu"]), 0,
+                             int(d.get("workgroup_lanes", 256) or 256), 0)
 
 
 def _batch_lib():
@@ -231,7 +238,7 @@ def _requests(arrays, seeds, H, eps):
 
 
 def _schedule_dict(s: rp_batch_schedule) -> dict:
-    return {f: int(getattr(s, f)) for f, _ in rp_batch_schedule._fields_}
+    return {f: int(getattr(s, f)) for f, _ in rp_batch_schedule._fields_ if f != "reserved"}
 
 
 class Batch:
@@ -299,10 +306,7 @@ def rp_batch_submit(arrays, *, seeds=None, H=None, eps: float = 0.5,
         reqs = requests
     else:
         reqs = _requests(arrays, seeds, H, eps)
-    sched = None
-    if schedule is not None:
-        sched = rp_batch_schedule(schedule["wave_cutoff"], schedule["table_ratio_x16"],
-                                  schedule["workgroups_per_cu"], 0)
+    sched = None if schedule is None else _schedule_struct(schedule)
     bid = ctypes.c_uint64(0)
     rc = _batch_lib().rp_batch_submit(reqs, len(arrays),
                                       ctypes.byref(sched) if sched is not None else None,
@@ -397,9 +401,7 @@ class Server:
         cfg.tick_us = tick_us
         cfg.auto_release = 1 if auto_release else 0
         if schedule:
-            cfg.schedule = rp_batch_schedule(schedule["wave_cutoff"],
-                                             schedule["table_ratio_x16"],
-                                             schedule["workgroups_per_cu"], 0)
+            cfg.schedule = _schedule_struct(schedule)
         h = ctypes.c_uint64(0)
         rc = _server_lib().rp_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != RP_OK:

@@ -43,18 +43,26 @@ namespace {
 
 using namespace rpdev;
 
-constexpr int BWG = 256;                 // threads per workgroup
-constexpr int BWAVES = BWG / 64;
+// Workgroups of 256 or 1024 lanes (a schedule choice); LDS for round state:
+// 32 KB per 256-lane workgroup, 64 KB per 1024-lane one, split in equal parts
+// between the waves in wave mode.
+template <int WGL> struct Shape {
+    static constexpr int WAVES = WGL / 64;
+    static constexpr uint32_t LDS_WORDS = WGL == 1024 ? 16384u : 8192u;
+    static constexpr uint32_t WAVE_WORDS = LDS_WORDS / WAVES;
+};
 constexpr int BM = 8;                    // swap slots per lane (maximum)
-constexpr uint32_t LDS_WORDS = 8192;     // 32 KB of round state per workgroup
-constexpr uint32_t WAVE_WORDS = LDS_WORDS / BWAVES;
-// Priorities hold the rank s - cnew in 24 bits.  A swap that enters the
-// window stays active at most k rounds (every round the highest active swap
-// commits, and no swap above it ever enters again), and the window moves down
-// by at most k per round, so ranks stay below k*k + k: within 24 bits for any
-// n once k <= 4095, with no rank throttle.
-constexpr uint32_t K_MAX_WG = BWG * BM;  // largest k of any request
-static_assert((uint64_t)K_MAX_WG * K_MAX_WG + K_MAX_WG < (1ull << RANKB), "ranks overflow");
+// Priorities are tag:4 | rank:28 with rank = s - cnew.  A swap that enters
+// the window stays active at most k rounds (every round the highest active
+// swap commits, and no swap above it ever enters again), and the window moves
+// down by at most k per round, so ranks stay below k*k + k: within 28 bits for
+// any n since k <= 1024 * BM, with no rank throttle.  The 4-bit tag makes the
+// values of a round exceed all older ones; the LDS slot array is cleared every
+// 16 rounds, which costs little in LDS.
+constexpr uint32_t BRANKB = 28;
+constexpr uint32_t BTAG_CYCLE = 16;
+constexpr uint32_t K_MAX_WG = 1024 * BM;  // largest k of any request
+static_assert((uint64_t)K_MAX_WG * K_MAX_WG + K_MAX_WG < (1ull << BRANKB), "ranks overflow");
 constexpr uint64_t BATCH_MAX_N = 1ull << 32;  // indices are 32-bit
 
 struct BatchReq {
@@ -81,11 +89,12 @@ struct BatchParams {
 
 // ------------------------------------------------------------ lane groups
 
-// Workgroup: 256 lanes, LDS scratch shared, barrier = __syncthreads.
-struct WGGroup {
+// Workgroup: WGL lanes, LDS scratch shared, barrier = __syncthreads.
+template <int WGL> struct WGGroup {
+    static constexpr int BWAVES = WGL / 64;
     uint32_t *lds;
     uint32_t *sh_scan;  // BWAVES words
-    __device__ uint32_t nlanes() const { return BWG; }
+    __device__ uint32_t nlanes() const { return WGL; }
     __device__ uint32_t lane() const { return threadIdx.x; }
     __device__ void sync() const { __syncthreads(); }
     // Exclusive prefix of x over the group; *total = sum.  Contains a
@@ -237,7 +246,7 @@ __device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_roun
         const uint32_t take = min(totF, cursor);
         const uint32_t cnew = cursor - take;
         const uint32_t par = (uint32_t)(rounds & 1);
-        const uint32_t tag = (uint32_t)(rounds & 255);
+        const uint32_t tag = (uint32_t)(rounds & (BTAG_CYCLE - 1));
         if (tag == 0 && rounds > 0) {
             // Tags restart: empty the slot array (every check of the last
             // round finished before the scan's barrier).
@@ -275,7 +284,7 @@ __device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_roun
         for (int m = 0; m < BM; m++) {
             if (src[m] != EMPTY) {
                 attempts++;
-                const uint32_t v = (tag << RANKB) | (src[m] - cnew);
+                const uint32_t v = (tag << BRANKB) | (src[m] - cnew);
                 __hip_atomic_fetch_max(&slots[slot1(tgt[m], T)], v, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 const uint32_t d = tgt[m] - cnew;
@@ -294,7 +303,7 @@ __device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_roun
                 continue;
             const uint32_t s = src[m], h = tgt[m];
             const uint32_t ds = s - cnew;
-            const uint32_t v = (tag << RANKB) | ds;
+            const uint32_t v = (tag << BRANKB) | ds;
             bool win = lds_ld(&slots[slot1(h, T)]) == v;
             if (ds < W)
                 win = win && !((lds_ld(&bm[par * bmw + (ds >> 5)]) >> (ds & 31u)) & 1u);
@@ -318,6 +327,7 @@ __device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_roun
     *status_out = status;
 }
 
+template <int BWAVES>
 __device__ __forceinline__ uint64_t sum_over_group_wg(uint64_t v, uint64_t *sh)
 {
     v = wave_sum64(v);
@@ -351,12 +361,13 @@ __device__ __forceinline__ void publish(const BatchParams &bp, const BatchReq &r
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <int EB>
-__global__ __launch_bounds__(BWG) void rp_batch_kernel(BatchParams bp)
+template <int EB, int WGL>
+__global__ __launch_bounds__(WGL) void rp_batch_kernel(BatchParams bp)
 {
-    __shared__ uint32_t lds[LDS_WORDS];
-    __shared__ uint32_t sh_scan[BWAVES];
-    __shared__ uint64_t sh_red[BWAVES];
+    using S = Shape<WGL>;
+    __shared__ uint32_t lds[S::LDS_WORDS];
+    __shared__ uint32_t sh_scan[S::WAVES];
+    __shared__ uint64_t sh_red[S::WAVES];
     __shared__ uint32_t sh_claim;
 
     // Every value that steers these loops is wave-uniform (held in scalar
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(BWG) void rp_batch_kernel(BatchParams bp)
     // keep re-running the previous request.
 
     // Workgroup mode: the largest requests, one per workgroup.
-    WGGroup wg{lds, sh_scan};
+    WGGroup<WGL> wg{lds, sh_scan};
     for (;;) {
         if (threadIdx.x == 0)
             sh_claim = __hip_atomic_fetch_add(&bp.claims[0], 1u, __ATOMIC_RELAXED,
@@ -382,16 +393,17 @@ __global__ __launch_bounds__(BWG) void rp_batch_kernel(BatchParams bp)
         uint32_t status = 0;
         if (r.n > 1 && !r.invalid)
             run_request<EB>(wg, r, (uint64_t)r.n + 64, &rounds, &attempts, &status);
-        attempts = sum_over_group_wg(attempts, sh_red);
-        rounds = sum_over_group_wg(r.T == 0 ? rounds : (threadIdx.x == 0 ? rounds : 0), sh_red);
+        attempts = sum_over_group_wg<S::WAVES>(attempts, sh_red);
+        rounds = sum_over_group_wg<S::WAVES>(r.T == 0 ? rounds : (threadIdx.x == 0 ? rounds : 0),
+                                             sh_red);
         if (threadIdx.x == 0)
             publish(bp, r, rounds, attempts, status);
         __syncthreads();
     }
-    // Wave mode: the rest, one per wave, each in its quarter of the LDS.
+    // Wave mode: the rest, one per wave, each in its share of the LDS.
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
-    WaveGroup wv{lds + wave * WAVE_WORDS};
+    WaveGroup wv{lds + wave * S::WAVE_WORDS};
     for (;;) {
         // Every lane adds (1 on lane 0, 0 elsewhere); lane 0's old value is
         // the claim.  No lane-divergent branch around the claim.
@@ -580,6 +592,7 @@ rp_batch_schedule default_schedule()
     s.wave_cutoff = (uint32_t)env_or("RP_BATCH_CUTOFF", 1 << 14);
     s.table_ratio_x16 = (uint32_t)env_or("RP_BATCH_RATIO16", 16);
     s.workgroups_per_cu = (uint32_t)env_or("RP_BATCH_WPC", 4);
+    s.workgroup_lanes = (uint32_t)env_or("RP_BATCH_LANES", 256);
     return s;
 }
 
@@ -589,11 +602,21 @@ rp_batch_schedule g_tuned_sched{};
 
 using BatchKernelFn = void (*)(BatchParams);
 
-BatchKernelFn pick_batch_kernel(uint32_t eb)
+uint32_t lanes_of(const rp_batch_schedule &s)
 {
-    if (eb == 4) return rp_batch_kernel<4>;
-    if (eb == 8) return rp_batch_kernel<8>;
-    return rp_batch_kernel<0>;
+    return s.workgroup_lanes == 1024 ? 1024u : 256u;
+}
+
+BatchKernelFn pick_batch_kernel(uint32_t eb, uint32_t lanes)
+{
+    if (lanes == 1024) {
+        if (eb == 4) return rp_batch_kernel<4, 1024>;
+        if (eb == 8) return rp_batch_kernel<8, 1024>;
+        return rp_batch_kernel<0, 1024>;
+    }
+    if (eb == 4) return rp_batch_kernel<4, 256>;
+    if (eb == 8) return rp_batch_kernel<8, 256>;
+    return rp_batch_kernel<0, 256>;
 }
 
 int launch_batch(const rp_batch_request *reqs, uint32_t count,
@@ -602,6 +625,7 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
     b->stream = stream;
     b->count = count;
     const double ratio = std::max(1u, sched.table_ratio_x16) / 16.0;
+    const uint32_t lanes = lanes_of(sched);
     uint32_t eb = 0;
     for (uint32_t i = 0; i < count; i++) {
         if (!valid_request(reqs[i]))
@@ -634,7 +658,9 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
         r.seed = q.seed;
         r.n = (uint32_t)q.n;
         r.eb = q.elem_bytes;
-        plan_request(q.n, q.eps, ratio, wgm ? BWG : 64, wgm ? LDS_WORDS : WAVE_WORDS,
+        plan_request(q.n, q.eps, ratio, wgm ? lanes : 64,
+                     wgm ? (lanes == 1024 ? Shape<1024>::LDS_WORDS : Shape<256>::LDS_WORDS)
+                         : (lanes == 1024 ? Shape<1024>::WAVE_WORDS : Shape<256>::WAVE_WORDS),
                      &r.k, &r.T, &r.bmw);
         r.wg_mode = wgm ? 1u : 0u;
         r.orig = order[i];
@@ -662,10 +688,10 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
             cus = prop.multiProcessorCount;
     }
-    const BatchKernelFn fn = pick_batch_kernel(eb);
+    const BatchKernelFn fn = pick_batch_kernel(eb, lanes);
     int occ = 1;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void *>(fn), BWG, 0);
+        &occ, reinterpret_cast<const void *>(fn), (int)lanes, 0);
     const uint32_t wpc = std::max(1u, std::min<uint32_t>(sched.workgroups_per_cu,
                                                          (uint32_t)std::max(occ, 1)));
     uint32_t grid = (uint32_t)cus * wpc;
@@ -677,7 +703,7 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
     bp.res = b->res;
     bp.done_flags = b->done + 1;
     if (count > 0) {
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(BWG), 0, stream, bp);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(lanes), 0, stream, bp);
         if (hipGetLastError() != hipSuccess)
             return RP_EDEVICE;
     }
@@ -825,7 +851,8 @@ int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream
     }
     const uint32_t cutoffs[] = {1u << 10, 1u << 12, 1u << 14, 1u << 16, 1u << 18, 0xFFFFFFFFu};
     const uint32_t ratios[] = {12, 16, 24};
-    const uint32_t wpcs[] = {2, 4, 8};
+    struct Shape_ { uint32_t lanes, wpc; };
+    const Shape_ shapes[] = {{256, 2}, {256, 4}, {256, 8}, {1024, 1}, {1024, 2}};
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -833,11 +860,12 @@ int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream
     rp_batch_schedule best = default_schedule();
     for (uint32_t c : cutoffs)
         for (uint32_t r16 : ratios)
-            for (uint32_t w : wpcs) {
+            for (const Shape_ &sh : shapes) {
                 rp_batch_schedule s{};
                 s.wave_cutoff = c;
                 s.table_ratio_x16 = r16;
-                s.workgroups_per_cu = w;
+                s.workgroups_per_cu = sh.wpc;
+                s.workgroup_lanes = sh.lanes;
                 float tot = 0.f;
                 bool ok = true;
                 for (int rep = 0; rep < 2 && ok; rep++) {

@@ -540,8 +540,15 @@ int launch_batched(Server &s, int cls)
         }
         const rp_batch_schedule &sc = s.cfg.schedule;
         const bool have_sched = sc.wave_cutoff || sc.table_ratio_x16 || sc.workgroups_per_cu;
-        rc = rp_batch_submit(br.data(), (uint32_t)br.size(), have_sched ? &sc : nullptr,
-                             s.streams[si], &L.batch_id);
+        // Large requests: one 1024-lane workgroup each (four times the active
+        // swaps of a 256-lane one, so a quarter of the rounds).
+        rp_batch_schedule large{};
+        large.wave_cutoff = 0;
+        large.table_ratio_x16 = have_sched && sc.table_ratio_x16 ? sc.table_ratio_x16 : 24;
+        large.workgroups_per_cu = 2;
+        large.workgroup_lanes = 1024;
+        const rp_batch_schedule *use = cls == 1 ? &large : (have_sched ? &sc : nullptr);
+        rc = rp_batch_submit(br.data(), (uint32_t)br.size(), use, s.streams[si], &L.batch_id);
     }
     if (rc != RP_OK) {
         fail_tickets(s, tickets, rc);

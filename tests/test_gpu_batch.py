@@ -36,7 +36,11 @@ SCHEDULES = [None,
              {"wave_cutoff": 1 << 24, "table_ratio_x16": 16, "workgroups_per_cu": 4},
              {"wave_cutoff": 0, "table_ratio_x16": 16, "workgroups_per_cu": 2},
              {"wave_cutoff": 1 << 12, "table_ratio_x16": 24, "workgroups_per_cu": 8},
-             {"wave_cutoff": 1 << 10, "table_ratio_x16": 12, "workgroups_per_cu": 1}]
+             {"wave_cutoff": 1 << 10, "table_ratio_x16": 12, "workgroups_per_cu": 1},
+             {"wave_cutoff": 1 << 12, "table_ratio_x16": 24, "workgroups_per_cu": 2,
+              "workgroup_lanes": 1024},
+             {"wave_cutoff": 0, "table_ratio_x16": 16, "workgroups_per_cu": 1,
+              "workgroup_lanes": 1024}]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
@@ -149,16 +153,18 @@ def test_config_4096_log_uniform_2p8_2p20():
         assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(sizes[i]), seeds[i])), i
 
 
-def test_large_request_in_a_batch():
-    """Requests far above the size of the rank field (2^24) run in workgroup
-    mode without a rank throttle; checked at sampled positions plus the
+@pytest.mark.parametrize("lanes", [256, 1024])
+def test_large_request_in_a_batch(lanes):
+    """Large requests (k up to 8192 active swaps in a 1024-lane workgroup)
+    run without a rank throttle; checked at sampled positions plus the
     permutation property."""
     sizes = [(1 << 25) + 7, 3000, (1 << 24) + 1, 70000]
     seeds = [91, 92, 93, 94]
     arrays = [torch.arange(n, dtype=torch.int32, device=DEV) for n in sizes]
     res = _run_batch(arrays, seeds, schedule={"wave_cutoff": 1 << 12,
                                               "table_ratio_x16": 16,
-                                              "workgroups_per_cu": 4})
+                                              "workgroups_per_cu": 4 if lanes == 256 else 2,
+                                              "workgroup_lanes": lanes})
     for i, n in enumerate(sizes):
         assert res[i]["status"] == 0
         assert res[i]["aux_words"] <= rp.rp_aux_bound_words(n, 0.5)
