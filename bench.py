@@ -17,6 +17,12 @@ from a SplitMix64 stream (seed 7), int64 A[i] = i, request seed 10^6 + id,
 eps = 0.5, through a server with a 64 GiB arena, once batched and once with
 one plain launch per request; it reports elements/s and p50/p99 latency.
 
+`--workload ablation` times the reservation variants (final, one reservation
+without the dense window, Algorithm 1's two reservations, the non-in-place
+linear array) on the n = 2^30 int64 workload, each checked byte-equal to the
+final variant's result, and sweeps the auxiliary bound at n = 10^8 int64 (the
+paper's aux-space table: 0.4 %, 1 %, 2 %, 4 % of n, plus smaller bounds).
+
 `--workload batch` measures the batched form instead: 4096 independent
 shuffles, n = floor(2^U) with U ~ Uniform[8, 20) drawn from a SplitMix64
 stream (seed 12345), int32 A[i] = i, instance seed 1000 + id, eps = 0.5, as
@@ -91,7 +97,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("plain", "batch", "serve"), default="plain")
+    ap.add_argument("--workload", choices=("plain", "batch", "serve", "ablation"),
+                    default="plain")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve workload: seconds of arrivals per rate")
     ap.add_argument("--rates", default="50,200,1000",
@@ -116,6 +123,8 @@ def main():
         run_batch(args, log)
     elif args.workload == "serve":
         run_serve(args, log)
+    elif args.workload == "ablation":
+        run_ablation(args, log)
     else:
         run_plain(args, log)
 
@@ -482,6 +491,101 @@ def run_serve(args, log):
                                "A[i]=i, seed 1e6+id, eps=0.5, 64 GiB arena",
                    "duration_s": args.duration, "rates": per_rate,
                    "value_is": f"batched elements/s at {rates[-1]:g} requests/s"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_ablation(args, log):
+    """Reservation variants and the auxiliary-space sweep (module docstring)."""
+    import math
+    import torch
+    import paper_2103_01216_amd as rp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(A, variant, eps, seed):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        st = None
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            h = rp.rp_shuffle_variant(A, variant=variant, seed=seed + i, eps=eps, stream=stream)
+            ev[i][1].record(stream)
+            st = h.get()
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+        return ms, st
+
+    n = WORKLOAD["n"]
+    A = torch.arange(n, dtype=torch.int64, device=dev)
+    ref = torch.arange(n, dtype=torch.int64, device=dev)
+    rp.rp_shuffle_inplace(ref, seed=WORKLOAD["seed"], eps=0.5, stream=stream, stats=False)
+    variants = {}
+    for name in ("final", "oneres", "twores", "linear"):
+        A.copy_(torch.arange(n, dtype=torch.int64, device=dev))
+        rp.rp_shuffle_variant(A, variant=name, seed=WORKLOAD["seed"], eps=0.5,
+                              stream=stream, stats=False)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(A, ref))
+        ms, st = timed(A, name, 0.5, 100)
+        variants[name] = {"ms": ms, "elements_per_s": n / (ms * 1e-3), "equal_to_final": same,
+                          "rounds": st["rounds"], "attempts": st["attempts"],
+                          "retries": st["retries"], "k": st["k"],
+                          "aux_words": st["aux_words"], "aux_bound_words": st["aux_bound_words"]}
+        log(f"n=2^30 {name}: {ms:.1f} ms, rounds {st['rounds']}, k {st['k']}, "
+            f"retries {st['retries']}, aux {st['aux_words']} words, equal to final: {same}")
+        if not same:
+            log("PARITY FAILURE")
+            sys.exit(1)
+    # The final variant at the paper's auxiliary fractions, same n.
+    big_aux = []
+    for label, frac in (("0.4%", 0.004), ("4%", 0.04)):
+        eps = -math.log(frac) / math.log(n)
+        ms, st = timed(A, "final", eps, 150)
+        big_aux.append({"aux": label, "eps": eps, "ms": ms, "rounds": st["rounds"],
+                        "k": st["k"], "aux_words": st["aux_words"],
+                        "aux_bound_words": st["aux_bound_words"]})
+        log(f"n=2^30 final, aux {label} (eps {eps:.4f}): {ms:.1f} ms, rounds {st['rounds']}, "
+            f"k {st['k']}")
+    del A, ref
+    torch.cuda.empty_cache()
+
+    n2 = 10**8
+    A = torch.arange(n2, dtype=torch.int64, device=dev)
+    sweep = []
+    points = [("0.4%", 0.004), ("1%", 0.01), ("2%", 0.02), ("4%", 0.04)]
+    for label, frac in points:
+        eps = -math.log(frac) / math.log(n2)
+        ms, st = timed(A, "final", eps, 200)
+        sweep.append({"aux": label, "eps": eps, "ms": ms, "rounds": st["rounds"], "k": st["k"],
+                      "aux_words": st["aux_words"], "aux_bound_words": st["aux_bound_words"]})
+        log(f"n=1e8 aux {label} (eps {eps:.4f}): {ms:.1f} ms, rounds {st['rounds']}, k {st['k']}")
+    for eps in (0.4, 0.5, 0.6, 0.75):
+        ms, st = timed(A, "final", eps, 300)
+        sweep.append({"aux": f"n^{1 - eps:.2f}", "eps": eps, "ms": ms, "rounds": st["rounds"],
+                      "k": st["k"], "aux_words": st["aux_words"],
+                      "aux_bound_words": st["aux_bound_words"]})
+        log(f"n=1e8 eps {eps}: {ms:.1f} ms, rounds {st['rounds']}, k {st['k']}, "
+            f"aux {st['aux_words']} words")
+    out = {
+        "metric": "reservation variants and auxiliary-space sweep (ms per shuffle)",
+        "value": variants["final"]["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": variants["final"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "variants at n=2^30 int64 eps=0.5 (seed mode); aux sweep of the "
+                               "final variant at n=1e8 int64",
+                   "variants": variants, "final_aux_n2p30": big_aux,
+                   "aux_sweep_n1e8": sweep},
     }
     print(json.dumps(out), flush=True)
 

@@ -130,6 +130,38 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
                        void *stream, rp_stats *stats);
 
 /*
+ * Reservation variants of the same operation, for comparing design choices
+ * (Section 7.4 and the appendix on the random permutation implementations:
+ * the versions differ in how the reservation array R is held and how many
+ * reservations a swap makes per round).  Every variant computes exactly the
+ * permutation of rp_shuffle_inplace; only rounds, retries and memory traffic
+ * differ.
+ *   RP_VARIANT_FINAL   the path of rp_shuffle_inplace: one reservation, on
+ *                      H[s], in a hashed slot array; the round's consecutive
+ *                      keys are checked in a dense window array
+ *   RP_VARIANT_ONERES  one reservation on H[s]; the source check also goes
+ *                      through the hashed slots (no dense window)
+ *   RP_VARIANT_TWORES  Algorithm 1 as printed: reservations on both s and
+ *                      H[s] (hashed); a swap commits when both hold its own
+ *                      priority
+ *   RP_VARIANT_LINEAR  the non-in-place scheme: R is an array of n 8-byte
+ *                      words (exact, never cleaned: the round number is part
+ *                      of every priority) and k is the largest the grid
+ *                      holds; eps does not bound its memory
+ * Arguments and errors as rp_shuffle_inplace; RP_EINVAL for an unknown
+ * variant.  stats->aux_words counts what the variant allocated (for
+ * RP_VARIANT_LINEAR it exceeds aux_bound_words).
+ */
+#define RP_VARIANT_FINAL 0
+#define RP_VARIANT_ONERES 1
+#define RP_VARIANT_TWORES 2
+#define RP_VARIANT_LINEAR 3
+
+int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
+                       const uint64_t *H, uint64_t seed, double eps, int variant,
+                       void *stream, rp_stats *stats);
+
+/*
  * Seed-mode swap targets on the device, for testing the exact integer path:
  * out[j] = splitmix64(seed ^ idx[j]) mod (idx[j] + 1) for j < count, with
  * idx[j] < 2^32.  idx and out are device arrays.  Stream-ordered.

@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
         L.rp_plan.argtypes = [u64, u32, ctypes.c_double, i32, ctypes.POINTER(rp_stats)]
         L.rp_shuffle_inplace.restype = i32
         L.rp_shuffle_inplace.argtypes = [vp, u64, u32, vp, u64, ctypes.c_double, vp, vp]
+        L.rp_shuffle_variant.restype = i32
+        L.rp_shuffle_variant.argtypes = [vp, u64, u32, vp, u64, ctypes.c_double, i32, vp, vp]
         L.rp_seed_targets.restype = i32
         L.rp_seed_targets.argtypes = [vp, u64, u64, vp, vp]
         _lib = L
@@ -121,6 +123,14 @@ class PendingStats:
         return _stats_dict(s)
 
 
+RP_VARIANT_FINAL = 0
+RP_VARIANT_ONERES = 1
+RP_VARIANT_TWORES = 2
+RP_VARIANT_LINEAR = 3
+VARIANTS = {"final": RP_VARIANT_FINAL, "oneres": RP_VARIANT_ONERES,
+            "twores": RP_VARIANT_TWORES, "linear": RP_VARIANT_LINEAR}
+
+
 def rp_shuffle_inplace(A, *, H=None, seed: int = 0, eps: float = 0.5,
                        stream=None, stats: bool = True):
     """Permute A (device tensor, first axis = records) in place.
@@ -130,6 +140,18 @@ def rp_shuffle_inplace(A, *, H=None, seed: int = 0, eps: float = 0.5,
     PendingStats (or None with stats=False).  Raises RpError on an error
     code; A is then untouched.
     """
+    return _shuffle(A, H, seed, eps, None, stream, stats)
+
+
+def rp_shuffle_variant(A, *, variant, H=None, seed: int = 0, eps: float = 0.5,
+                       stream=None, stats: bool = True):
+    """rp_shuffle_inplace under one of the reservation variants
+    (RP_VARIANT_* or a name in VARIANTS); same result, different cost."""
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    return _shuffle(A, H, seed, eps, v, stream, stats)
+
+
+def _shuffle(A, H, seed, eps, variant, stream, stats):
     import torch
     n, eb = _record_geometry(A)
     if stream is None:
@@ -146,11 +168,16 @@ def rp_shuffle_inplace(A, *, H=None, seed: int = 0, eps: float = 0.5,
         host = torch.zeros(ctypes.sizeof(rp_stats) // 8, dtype=torch.int64,
                            pin_memory=True)
         sptr = ctypes.c_void_p(host.data_ptr())
-    rc = lib().rp_shuffle_inplace(ctypes.c_void_p(A.data_ptr() if n else 0), n, eb,
-                                  hptr, seed & (2**64 - 1), eps,
-                                  ctypes.c_void_p(stream.cuda_stream), sptr)
+    if variant is None:
+        rc = lib().rp_shuffle_inplace(ctypes.c_void_p(A.data_ptr() if n else 0), n, eb,
+                                      hptr, seed & (2**64 - 1), eps,
+                                      ctypes.c_void_p(stream.cuda_stream), sptr)
+    else:
+        rc = lib().rp_shuffle_variant(ctypes.c_void_p(A.data_ptr() if n else 0), n, eb,
+                                      hptr, seed & (2**64 - 1), eps, variant,
+                                      ctypes.c_void_p(stream.cuda_stream), sptr)
     if rc != RP_OK:
-        raise RpError(rc, "rp_shuffle_inplace")
+        raise RpError(rc, "rp_shuffle_inplace" if variant is None else "rp_shuffle_variant")
     return PendingStats(host, stream) if stats else None
 
 

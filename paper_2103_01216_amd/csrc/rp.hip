@@ -108,6 +108,9 @@ struct Params {
     uint32_t *err;
     uint64_t *dstats;    // rp_stats laid out as 12 x 64-bit words
     uint64_t max_rounds;
+    uint32_t variant;    // RP_VARIANT_*: how reservations are held and checked
+    uint32_t pad;
+    uint64_t *R64;       // RP_VARIANT_LINEAR: one priority word per position
 };
 
 // rp_stats word indices
@@ -204,7 +207,12 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 
     const uint32_t G = gridDim.x, w = blockIdx.x, t = threadIdx.x;
     const uint32_t wave = t >> 6, lane = t & 63;
-    const uint32_t W = p.bmw * 32u;  // dense window width in keys
+    // Dense window only in the final variant: the one-reservation variant
+    // checks sources through the hashed slots, the two-reservation one
+    // reserves sources there, the linear one has exact per-position words.
+    const uint32_t W = p.variant == RP_VARIANT_FINAL ? p.bmw * 32u : 0u;
+    const bool linear = p.variant == RP_VARIANT_LINEAR;
+    const bool twores = p.variant == RP_VARIANT_TWORES;
 
     uint32_t src[M], tgt[M];
     bool usable[M];
@@ -304,7 +312,7 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 
         // Every TAG_CYCLE rounds: reset the reservation array behind an
         // extra barrier, so that tags restart from 0 over an empty array.
-        if (tag == 0 && rounds > 0) {
+        if (tag == 0 && rounds > 0 && !linear) {
             for (uint32_t i = w * WG + t; i < p.T; i += G * WG)
                 clear_rmw(&p.slots[i]);
             if (!plain_barrier(p, ++epoch, sh_res)) {
@@ -352,11 +360,22 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
         for (int m = 0; m < M; m++) {
             if (src[m] != EMPTY) {
                 act++;
+                if (linear) {
+                    // round + 1 in the high word: later rounds beat every
+                    // older value, so the array is never cleaned.
+                    const uint64_t v64 = ((rounds + 1) << 32) | (src[m] - cnew);
+                    __hip_atomic_fetch_max(&p.R64[tgt[m]], v64, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    continue;
+                }
                 const uint32_t v = (tag << RANKB) | (src[m] - cnew);
                 __hip_atomic_fetch_max(&p.slots[slot1(tgt[m], p.T)], v,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (p.choices > 1)
                     __hip_atomic_fetch_max(&p.slots[slot2(tgt[m], p.T)], v,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (twores)
+                    __hip_atomic_fetch_max(&p.slots[slot1(src[m], p.T)], v,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t d = tgt[m] - cnew;
                 if (tgt[m] >= cnew && d < W)
@@ -412,13 +431,22 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             if (src[m] == EMPTY)
                 continue;
             const uint32_t s = src[m], h = tgt[m];
-            t1[m] = ld(&p.slots[slot1(h, p.T)]);
-            t2[m] = (p.choices > 1) ? ld(&p.slots[slot2(h, p.T)]) : 0u;
             const uint32_t ds = s - cnew;  // s >= cnew for every active swap
             if (EB != 0 && !p.hoist) {
                 r_s[m].load(p.A, s);
                 r_h[m].load(p.A, h);
             }
+            if (linear) {
+                // (t2:t1) = R[H[s]], (q2:q1) = R[s]
+                const uint64_t a = ld(&p.R64[h]), b = ld(&p.R64[s]);
+                t1[m] = (uint32_t)a;
+                t2[m] = (uint32_t)(a >> 32);
+                q1[m] = (uint32_t)b;
+                q2[m] = (uint32_t)(b >> 32);
+                continue;
+            }
+            t1[m] = ld(&p.slots[slot1(h, p.T)]);
+            t2[m] = (p.choices > 1) ? ld(&p.slots[slot2(h, p.T)]) : 0u;
             if (ds < W) {
                 q1[m] = ld(&p.bm[(uint64_t)par * p.bmw + (ds >> 5)]);
             } else {
@@ -442,6 +470,14 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                 win = win && !((q1[m] >> (ds & 31u)) & 1u);
             else
                 win = win && (q1[m] <= v || (two && q2[m] <= v));
+            if (twores)  // Algorithm 1: both reservations must hold
+                win = (t1[m] == v) && (q1[m] == v);
+            if (linear) {
+                // exact: the maximum on H[s] is this swap, and no swap of
+                // this round reserved s
+                const uint32_t rid = (uint32_t)(rounds + 1);
+                win = t2[m] == rid && t1[m] == ds && q2[m] != rid;
+            }
             if (win) {
                 if (EB != 0) {
                     r_h[m].store(p.A, s);
@@ -578,6 +614,30 @@ int env_int(const char *name, int dflt)
 {
     const char *v = getenv(name);
     return v && *v ? atoi(v) : dflt;
+}
+
+// The linear variant: exact n-word array, as many active swaps as the grid
+// holds (up to n), no hashed slots or dense window.
+int choose_linear_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
+                       Plan *pl)
+{
+    std::memset(pl, 0, sizeof(*pl));
+    pl->bound = rp_aux_bound_words(n, eps);
+    pl->eb_class = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
+    const int slot_opts[4] = {1, 2, 4, 8};
+    int mi = 0;
+    while (mi < 3 && n > (uint64_t)cus * occ_by_m[mi] * WG * slot_opts[mi])
+        mi++;
+    const uint64_t M = slot_opts[mi];
+    const uint64_t gmax = std::min<uint64_t>(MAXG, (uint64_t)cus * occ_by_m[mi]);
+    const uint64_t G = std::max<uint64_t>(1, std::min<uint64_t>(gmax, (n + WG * M - 1) / (WG * M)));
+    pl->G = (uint32_t)G;
+    pl->M = (uint32_t)M;
+    pl->k = (uint32_t)std::min<uint64_t>(n, G * WG * M);
+    pl->T = 0;
+    pl->bmw = 0;
+    pl->aux_bytes = n * 8 + (G > 1 ? 2 * G * 8 : 0) + 8;
+    return RP_OK;
 }
 
 int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
@@ -778,13 +838,18 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
     return RP_OK;
 }
 
-int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
-                       const uint64_t *H, uint64_t seed, double eps,
-                       void *stream_, rp_stats *stats)
+}  // extern "C"
+
+namespace {
+
+int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, uint64_t seed,
+                 double eps, int variant, void *stream_, rp_stats *stats)
 {
     int rc = validate(A, n, elem_bytes, eps);
     if (rc != RP_OK)
         return rc;
+    if (variant < RP_VARIANT_FINAL || variant > RP_VARIANT_LINEAR)
+        return RP_EINVAL;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     if (n <= 1) {
         if (stats) {
@@ -805,7 +870,8 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
     for (int a = 0; a < 4; a++)
         occ[a] = di.occ[a][eb_index(ebc)];
     Plan pl;
-    rc = choose_plan(n, elem_bytes, eps, di.cus, occ, &pl);
+    rc = variant == RP_VARIANT_LINEAR ? choose_linear_plan(n, elem_bytes, eps, di.cus, occ, &pl)
+                                      : choose_plan(n, elem_bytes, eps, di.cus, occ, &pl);
     if (rc != RP_OK)
         return rc;
 
@@ -821,8 +887,10 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
     uint64_t *dstats = reinterpret_cast<uint64_t *>(base + aux_bytes);
     rp_stats hs;
     fill_host_stats(pl, &hs);
-    rp_init_kernel<<<64, 256, 0, stream>>>(reinterpret_cast<uint32_t *>(base),
-                                           aux_bytes / 4, dstats, hs);
+    const uint32_t init_blocks =
+        (uint32_t)std::min<uint64_t>(8192, std::max<uint64_t>(64, aux_bytes / 4 / (256 * 16)));
+    rp_init_kernel<<<init_blocks, 256, 0, stream>>>(reinterpret_cast<uint32_t *>(base),
+                                                    aux_bytes / 4, dstats, hs);
     if (hipGetLastError() != hipSuccess) {
         (void)hipFreeAsync(mem, stream);
         return RP_EDEVICE;
@@ -836,14 +904,25 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
     p.eb = elem_bytes;
     p.k = pl.k;
     p.T = pl.T;
-    p.choices = (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)));
+    p.choices = variant == RP_VARIANT_FINAL
+                    ? (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)))
+                    : 1u;
+    p.variant = (uint32_t)variant;
     p.hoist = env_int("RP_HOIST", 1) ? 1u : 0u;
     p.bmw = pl.bmw;
     p.dstats = dstats;
     p.max_rounds = n + 64;
-    // Carve the counted words: [slots | bm | flags | err].
+    // Carve the counted words: [slots | bm | flags | err], or for the linear
+    // variant [R (n words) | flags | err].
     unsigned char *cur = base;
-    if (!pl.single) {
+    if (variant == RP_VARIANT_LINEAR) {
+        p.R64 = reinterpret_cast<uint64_t *>(cur);
+        cur += n * 8;
+        if (pl.G > 1) {
+            p.flags = reinterpret_cast<uint64_t *>(cur);
+            cur += 2ull * pl.G * 8;
+        }
+    } else if (!pl.single) {
         p.slots = reinterpret_cast<uint32_t *>(cur);
         cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
         p.bm = reinterpret_cast<uint32_t *>(cur);
@@ -898,6 +977,24 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
     if (hipFreeAsync(mem, stream) != hipSuccess)
         return RP_EDEVICE;
     return RP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
+                       const uint64_t *H, uint64_t seed, double eps,
+                       void *stream, rp_stats *stats)
+{
+    return shuffle_impl(A, n, elem_bytes, H, seed, eps, RP_VARIANT_FINAL, stream, stats);
+}
+
+int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
+                       const uint64_t *H, uint64_t seed, double eps, int variant,
+                       void *stream, rp_stats *stats)
+{
+    return shuffle_impl(A, n, elem_bytes, H, seed, eps, variant, stream, stats);
 }
 
 int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,

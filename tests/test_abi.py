@@ -117,3 +117,10 @@ def test_records_generator_host_device_agree():
     rec = workloads.records64(64, "cpu", start=1000).numpy().view(np.uint32)
     assert np.array_equal(rec, workloads.records64_numpy(np.arange(1000, 1064)))
     assert rec[5, 0] == 1005
+
+
+def test_variant_rejects_unknown():
+    L = rp.lib()
+    assert L.rp_shuffle_variant(None, 0, 8, None, 0, 0.5, 7, None, None) == rp.RP_EINVAL
+    assert L.rp_shuffle_variant(None, 0, 8, None, 0, 0.5, -1, None, None) == rp.RP_EINVAL
+    assert L.rp_shuffle_variant(None, 0, 8, None, 0, 1.5, 0, None, None) == rp.RP_EINVAL
