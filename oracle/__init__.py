@@ -13,6 +13,11 @@ Contents
   A[H[i]], 0 <= H[i] <= i), its seed-mode targets
   H[i] = splitmix64(seed ^ i) mod (i+1), and a sampled form that returns, for
   chosen output positions, the source index of the record that lands there.
+* ``list_oracle.c`` (plain C): list ranking by walking each list (the
+  definition), and the relaxed-PIP list contraction of Section 4.2 --
+  Algorithm 2 applied to blocks of k elements in index order -- with the
+  per-element contraction records (neighbours at splice time, offset to the
+  left one, round).
 * ``alg1.py`` (pure Python, small n): the round structure of the paper's
   Algorithm 1 (parallel Knuth shuffle by deterministic reservations) and its
   relaxed-PIP form that works on the first K unfinished swaps per round.
@@ -26,7 +31,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "knuth_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("knuth_oracle.c", "list_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -36,12 +41,12 @@ _vp = ctypes.c_void_p
 
 
 def build(force: bool = True) -> str:
-    """Compile knuth_oracle.c with gcc into oracle/liboracle.so."""
+    """Compile the oracle's C files with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-             "-o", tmp, _SRC])
+             "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -145,3 +150,50 @@ def sample_sources(n: int, positions, *, H: np.ndarray | None = None,
     if rc != 0:
         raise ValueError("bad sample positions or targets")
     return out
+
+
+# ------------------------------------------------------------- list oracle
+
+NIL = 0xFFFFFFFF
+
+
+def list_rank(prev: np.ndarray, nxt: np.ndarray) -> np.ndarray:
+    """Position of every element in its list (heads 0), by walking the lists."""
+    prev = np.ascontiguousarray(prev, dtype=np.uint32)
+    nxt = np.ascontiguousarray(nxt, dtype=np.uint32)
+    n = prev.shape[0]
+    rank = np.empty(n, dtype=np.uint64)
+    lib = _load()
+    lib.oracle_list_rank.restype = ctypes.c_int
+    lib.oracle_list_rank.argtypes = [_vp, _vp, _u64, _vp]
+    if lib.oracle_list_rank(_ptr(prev), _ptr(nxt), n, _ptr(rank)) != 0:
+        raise ValueError("malformed list (inconsistent links or a cycle)")
+    return rank
+
+
+def list_contract(prev: np.ndarray, nxt: np.ndarray, k: int, *, seed: int = 0,
+                  prio: np.ndarray | None = None) -> dict:
+    """The relaxed-PIP list contraction (blocks of k elements in index order,
+    Algorithm 2 inside each block).  Returns the per-element records
+    left, right, offset, round and the total number of rounds."""
+    prev = np.ascontiguousarray(prev, dtype=np.uint32)
+    nxt = np.ascontiguousarray(nxt, dtype=np.uint32)
+    n = prev.shape[0]
+    left = np.empty(n, dtype=np.uint32)
+    right = np.empty(n, dtype=np.uint32)
+    offset = np.empty(n, dtype=np.uint64)
+    rnd = np.empty(n, dtype=np.uint32)
+    total = ctypes.c_uint64(0)
+    lib = _load()
+    lib.oracle_list_contract.restype = ctypes.c_int
+    lib.oracle_list_contract.argtypes = [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _vp, _vp,
+                                         _vp, ctypes.POINTER(_u64)]
+    pr = None if prio is None else np.ascontiguousarray(prio, dtype=np.uint64)
+    rc = lib.oracle_list_contract(_ptr(prev), _ptr(nxt), None if pr is None else _ptr(pr),
+                                  seed & (2**64 - 1), n, int(k), _ptr(left), _ptr(right),
+                                  _ptr(offset), _ptr(rnd), ctypes.byref(total))
+    if rc != 0:
+        raise ValueError("malformed list or k = 0")
+    return {"left": left, "right": right, "offset": offset, "round": rnd,
+            "rounds": int(total.value)}
+
