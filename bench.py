@@ -23,6 +23,10 @@ linear array) on the n = 2^30 int64 workload, each checked byte-equal to the
 final variant's result, and sweeps the auxiliary bound at n = 10^8 int64 (the
 paper's aux-space table: 0.4 %, 1 %, 2 %, 4 % of n, plus smaller bounds).
 
+`--workload list` ranks one random list of n = 10^8 elements (two 64-bit
+pointer words each, the paper's list-contraction inputs) by in-place list
+contraction, at several auxiliary bounds, checked against the CPU oracle.
+
 `--workload batch` measures the batched form instead: 4096 independent
 shuffles, n = floor(2^U) with U ~ Uniform[8, 20) drawn from a SplitMix64
 stream (seed 12345), int32 A[i] = i, instance seed 1000 + id, eps = 0.5, as
@@ -97,7 +101,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("plain", "batch", "serve", "ablation"),
+    ap.add_argument("--workload", choices=("plain", "batch", "serve", "ablation", "list"),
                     default="plain")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve workload: seconds of arrivals per rate")
@@ -125,6 +129,8 @@ def main():
         run_serve(args, log)
     elif args.workload == "ablation":
         run_ablation(args, log)
+    elif args.workload == "list":
+        run_list(args, log)
     else:
         run_plain(args, log)
 
@@ -587,6 +593,100 @@ def run_ablation(args, log):
                    "variants": variants, "final_aux_n2p30": big_aux,
                    "aux_sweep_n1e8": sweep},
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_list(args, log):
+    """List ranking by in-place list contraction (module docstring)."""
+    import math
+    import numpy as np
+    import torch
+    import paper_2103_01216_amd as rp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    n = 10**8
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    order = torch.randperm(n, device=dev, generator=g)       # the list's order
+    nil = (1 << 32) - 1
+    src = torch.empty((n, 2), dtype=torch.int64, device=dev)
+    src[order[1:], 0] = order[:-1]
+    src[order[0], 0] = nil
+    src[order[:-1], 1] = order[1:]
+    src[order[-1], 1] = nil
+    want = torch.empty(n, dtype=torch.int64, device=dev)
+    want[order] = torch.arange(n, dtype=torch.int64, device=dev)
+    del order
+    rec = src.clone()
+    rank = torch.empty(n, dtype=torch.int64, device=dev)
+    log("list: n = 1e8, one random list")
+    points = [("n^0.5", 0.5), ("1.4% of n", -math.log(0.014) / math.log(n)), ("n^0.75", 0.25)]
+    results = []
+    for label, eps in points:
+        rec.copy_(src)
+        _, st = rp.rp_list_rank(rec, seed=11, eps=eps, rank=rank, stream=stream)
+        ok = bool(torch.equal(rank, want))
+        if not ok or st["status"] != 0:
+            log(f"PARITY FAILURE at eps {eps}")
+            sys.exit(1)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for i in range(args.steps):
+            rec.copy_(src)
+            ev[i][0].record(stream)
+            rp.rp_list_rank(rec, seed=11 + i, eps=eps, rank=rank, stream=stream, stats=False)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+        results.append({"aux": label, "eps": eps, "ms": ms, "elements_per_s": n / (ms * 1e-3),
+                        "k": st["k"], "phases": st["phases"],
+                        "contract_rounds": st["contract_rounds"],
+                        "rebuild_rounds": st["rebuild_rounds"], "grid": st["grid"],
+                        "aux_words": st["aux_words"], "ranks_exact": ok})
+        log(f"  aux {label} (eps {eps:.3f}): {ms:.1f} ms, k {st['k']}, phases {st['phases']}, "
+            f"rounds {st['contract_rounds']} + {st['rebuild_rounds']}, grid {st['grid']}")
+    best = min(results, key=lambda r: r["ms"])
+    # 48 B per element: the two pointer words read and written once, one rank
+    # written and one rank read
+    alg = 48 * n
+    out = {
+        "metric": "list ranking by in-place list contraction, elements/s (n=1e8)",
+        "value": best["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": best["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "uint64",
+        "data": "synthetic",
+        "config": {"workload": "one random list of 1e8 elements (torch.randperm, seed 7), "
+                               "(prev, next) 64-bit words, seed-mode priorities",
+                   "points": results},
+        "roofline": {"bound": "hbm", "achieved": alg / (best["ms"] * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": alg / (best["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "rp_list_kernel", "algorithmic_bytes_per_launch": alg},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        m = 10**7
+        perm = np.random.default_rng(7).permutation(m).astype(np.uint32)
+        prev = np.full(m, nil, dtype=np.uint32)
+        nxt = np.full(m, nil, dtype=np.uint32)
+        prev[perm[1:]] = perm[:-1]
+        nxt[perm[:-1]] = perm[1:]
+        t0 = time.perf_counter()
+        oracle.list_rank(prev, nxt)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m / dt, "unit": "elements/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "sequential walk of one random list of 1e7 elements"}
+        log(f"cpu oracle: 1e7-element list walked in {dt:.2f} s")
     print(json.dumps(out), flush=True)
 
 

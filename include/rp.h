@@ -250,6 +250,50 @@ int rp_batch_results(uint64_t batch_id, rp_batch_result *out);
 int rp_batch_release(uint64_t batch_id);
 
 /* ------------------------------------------------------------------------
+ * List ranking by in-place list contraction (Section 4.2: list contraction
+ * has the Decomposable Property, so Algorithm 2 can be applied to
+ * n^(1-eps) elements at a time).
+ *
+ * rec: device array of 2n words, element i's (prev, next) pair.  On input
+ * the low 32 bits of rec[2i] and rec[2i+1] are the previous and next
+ * element (0xFFFFFFFF = none; any number of disjoint lists; the high bits
+ * are ignored).  The elements are contracted in blocks of
+ * k = floor(n^(1-eps)) indices (block j = [jk, (j+1)k)); inside a block,
+ * rounds of Algorithm 2 splice out every element whose key
+ * (block, priority, index) is below both current neighbours' keys; list
+ * heads are never spliced.  Priorities: prio[i] (device, may be NULL) or
+ * splitmix64(seed ^ i).  On return the pair of every non-head element holds
+ * its record in the contraction tree, overwriting the input pointers:
+ *   rec[2i]   = L | (offset << 32): L = left neighbour when it was spliced,
+ *               offset = its distance from L in the list
+ *   rec[2i+1] = R | (round << 32): R = right neighbour when it was spliced,
+ *               round = the round of its block in which it went
+ * A head's rec[2h] is unchanged and rec[2h+1] = 0xFFFFFFFF | (length << 32),
+ * the number of elements of its list.
+ * rank (device, n words, caller-owned) receives every element's position in
+ * its list (heads 0).
+ * Auxiliary memory: barrier flags and four words, at most
+ * max(floor(n^(1-eps)), 4) 8-byte words.  Errors: RP_EINVAL for bad
+ * arguments or inconsistent links (checked before anything is written);
+ * RP_ENOMEM; RP_EDEVICE.  A cycle (links consistent, no head) is found
+ * during the contraction: stats->status = RP_EINVAL, rec partly rewritten.
+ * With stats != NULL (host) the call waits for the stream to fill it.
+ * ------------------------------------------------------------------------ */
+typedef struct rp_list_stats {
+    uint64_t k;                  /* block size */
+    uint64_t aux_words;          /* 8-byte words allocated */
+    uint64_t aux_bound_words;    /* floor(n^(1-eps)) */
+    uint64_t phases;             /* blocks contracted */
+    uint64_t contract_rounds;    /* rounds of Algorithm 2, all blocks */
+    uint64_t rebuild_rounds;     /* reconstruction steps */
+    uint64_t grid;               /* workgroups */
+    int64_t status;              /* RP_OK, RP_EINVAL (cycle), RP_ETIMEOUT */
+} rp_list_stats;
+
+int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed, double eps,
+                 uint64_t *rank, void *stream, rp_list_stats *stats);
+
+/* ------------------------------------------------------------------------
  * Serving form: a request loop on one device.
  *
  * The paper motivates in-place algorithms by the limited memory of a single

@@ -506,3 +506,53 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------ list ranking
+
+LIST_NIL = 0xFFFFFFFF
+
+
+class rp_list_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("k", "aux_words", "aux_bound_words", "phases", "contract_rounds",
+                 "rebuild_rounds", "grid")] + [("status", ctypes.c_int64)]
+
+
+def rp_list_rank(rec, *, prio=None, seed: int = 0, eps: float = 0.5, rank=None,
+                 stream=None, stats: bool = True):
+    """List ranking by in-place list contraction (rp_list_rank of include/rp.h).
+
+    rec: contiguous (n, 2) 64-bit device tensor of (prev, next) pairs (low 32
+    bits; 0xFFFFFFFF = none), overwritten with the contraction records.
+    Returns (rank tensor, stats dict or None).
+    """
+    import torch
+    L = lib()
+    if not getattr(L, "_list_ready", False):
+        vp = ctypes.c_void_p
+        L.rp_list_rank.restype = ctypes.c_int
+        L.rp_list_rank.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64, ctypes.c_double,
+                                   vp, vp, ctypes.POINTER(rp_list_stats)]
+        L._list_ready = True
+    if not rec.is_cuda or not rec.is_contiguous() or rec.element_size() != 8 or \
+            rec.dim() != 2 or rec.shape[1] != 2:
+        raise ValueError("rec must be a contiguous (n, 2) 64-bit device tensor")
+    n = rec.shape[0]
+    if prio is not None and (not prio.is_cuda or prio.element_size() != 8 or prio.numel() != n
+                             or not prio.is_contiguous()):
+        raise ValueError("prio must be a contiguous device tensor of n 64-bit priorities")
+    if rank is None:
+        rank = torch.empty(n, dtype=torch.int64, device=rec.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(rec.device)
+    st = rp_list_stats() if stats else None
+    rc = L.rp_list_rank(ctypes.c_void_p(rec.data_ptr() if n else 0), n,
+                        ctypes.c_void_p(prio.data_ptr()) if prio is not None else None,
+                        seed & (2**64 - 1), eps,
+                        ctypes.c_void_p(rank.data_ptr() if n else 0),
+                        ctypes.c_void_p(stream.cuda_stream),
+                        ctypes.byref(st) if st is not None else None)
+    if rc != RP_OK:
+        raise RpError(rc, "rp_list_rank")
+    return rank, ({f: int(getattr(st, f)) for f, _ in rp_list_stats._fields_} if st else None)

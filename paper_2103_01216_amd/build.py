@@ -12,7 +12,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", f) for f in ("rp.hip", "rp_batch.hip", "rp_serve.hip")]
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("rp.hip", "rp_batch.hip", "rp_serve.hip", "rp_list.hip")]
 LIB = os.path.join(PKG, "librp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
