@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="batch workload: skip the one-launch-per-instance comparison")
     ap.add_argument("--schedule", default=None,
-                    help="batch workload: CUTOFF,RATIO16,WPC instead of autotuning")
+                    help="batch workload: CUTOFF,RATIO16,WPC[,LANES[,LATE]] instead of autotuning")
     args = ap.parse_args()
 
     def log(msg):
@@ -258,9 +258,10 @@ def run_batch(args, log):
         f"(n from {sizes.min()} to {sizes.max()})")
 
     if args.schedule:
-        c, r16, w = (int(x) for x in args.schedule.split(","))
-        sched = {"wave_cutoff": c, "table_ratio_x16": r16, "workgroups_per_cu": w,
-                 "tuned_ms_x1000": 0}
+        v = [int(x) for x in args.schedule.split(",")]
+        sched = {"wave_cutoff": v[0], "table_ratio_x16": v[1], "workgroups_per_cu": v[2],
+                 "workgroup_lanes": v[3] if len(v) > 3 else 256,
+                 "late_loads": v[4] if len(v) > 4 else 0, "tuned_ms_x1000": 0}
         log(f"schedule given: {sched}")
     else:
         t0 = time.perf_counter()

@@ -202,14 +202,16 @@ typedef struct rp_batch_result {
  * workgroups_per_cu = resident workgroups per compute unit (at most what the
  * workgroup size allows); workgroup_lanes = 256 or 1024 (0: 256) -- a
  * 1024-lane workgroup holds four times as many active swaps of one request,
- * so a large request needs a quarter of the rounds. */
+ * so a large request needs a quarter of the rounds; late_loads = 1 reads a
+ * swap's two records only once it has won its round (fewer random reads,
+ * longer rounds), 0 reads them before the decision. */
 typedef struct rp_batch_schedule {
     uint32_t wave_cutoff;
     uint32_t table_ratio_x16;
     uint32_t workgroups_per_cu;
     uint32_t tuned_ms_x1000;  /* out: best trial time in microseconds */
     uint32_t workgroup_lanes;
-    uint32_t reserved;        /* 0 */
+    uint32_t late_loads;
 } rp_batch_schedule;
 
 /*

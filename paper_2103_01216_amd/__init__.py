@@ -214,13 +214,14 @@ class rp_batch_result(ctypes.Structure):
 class rp_batch_schedule(ctypes.Structure):
     _fields_ = [("wave_cutoff", ctypes.c_uint32), ("table_ratio_x16", ctypes.c_uint32),
                 ("workgroups_per_cu", ctypes.c_uint32), ("tuned_ms_x1000", ctypes.c_uint32),
-                ("workgroup_lanes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("workgroup_lanes", ctypes.c_uint32), ("late_loads", ctypes.c_uint32)]
 
 
 def _schedule_struct(d: dict) -> rp_batch_schedule:
     return rp_batch_schedule(int(d["wave_cutoff"]), int(d["table_ratio_x16"]),
                              int(d["workgroups_per_cu"]), 0,
-                             int(d.get("workgroup_lanes", 256) or 256), 0)
+                             int(d.get("workgroup_lanes", 256) or 256),
+                             int(d.get("late_loads", 0)))
 
 
 def _batch_lib():
@@ -265,7 +266,7 @@ def _requests(arrays, seeds, H, eps):
 
 
 def _schedule_dict(s: rp_batch_schedule) -> dict:
-    return {f: int(getattr(s, f)) for f, _ in rp_batch_schedule._fields_ if f != "reserved"}
+    return {f: int(getattr(s, f)) for f, _ in rp_batch_schedule._fields_}
 
 
 class Batch:

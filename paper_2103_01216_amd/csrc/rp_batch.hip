@@ -85,6 +85,7 @@ struct BatchParams {
     uint32_t *claims;       // [0]: next workgroup request, [1]: next wave request
     rp_batch_result *res;   // indexed by the caller's order
     uint32_t *done_flags;   // host-visible: per request (caller's order)
+    uint32_t late;          // 1: records read after the decision
 };
 
 // ------------------------------------------------------------ lane groups
@@ -183,7 +184,7 @@ __device__ __forceinline__ void pswap_generic(unsigned char *A, uint32_t eb,
 // Run one request on group g.  Returns (rounds, attempts) through pointers
 // valid on every lane.
 template <int EB, typename Group>
-__device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_rounds,
+__device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_rounds, bool late,
                             uint64_t *rounds_out, uint64_t *attempts_out,
                             uint32_t *status_out)
 {
@@ -270,8 +271,11 @@ __device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_roun
                 }
             }
         }
+        // Records are read here, before the decision, unless `late`: then
+        // only the round's winners read them, after the decision (fewer
+        // random reads when a retry would read its records again).
         PRec<EB == 0 ? 4 : EB> r_s[BM], r_h[BM];
-        if (EB != 0) {
+        if (EB != 0 && !late) {
 #pragma unroll
             for (int m = 0; m < BM; m++)
                 if (src[m] != EMPTY) {
@@ -296,28 +300,44 @@ __device__ void run_request(const Group &g, const BatchReq &r, uint64_t max_roun
         for (uint32_t i = lane; i < bmw; i += L)
             lds_st(&bm[(par ^ 1u) * bmw + i], 0u);
         g.sync();
-        // commit
+        // commit: decide every slot, then (late) read the winners' records,
+        // then write them swapped
+        bool win[BM];
 #pragma unroll
         for (int m = 0; m < BM; m++) {
+            win[m] = false;
             if (src[m] == EMPTY)
                 continue;
             const uint32_t s = src[m], h = tgt[m];
             const uint32_t ds = s - cnew;
             const uint32_t v = (tag << BRANKB) | ds;
-            bool win = lds_ld(&slots[slot1(h, T)]) == v;
+            bool w = lds_ld(&slots[slot1(h, T)]) == v;
             if (ds < W)
-                win = win && !((lds_ld(&bm[par * bmw + (ds >> 5)]) >> (ds & 31u)) & 1u);
+                w = w && !((lds_ld(&bm[par * bmw + (ds >> 5)]) >> (ds & 31u)) & 1u);
             else
-                win = win && lds_ld(&slots[slot1(s, T)]) <= v;
-            if (win) {
-                if (EB != 0) {
-                    r_h[m].store(r.A, s);
-                    r_s[m].store(r.A, h);
-                } else {
-                    pswap_generic(r.A, r.eb, s, h);
+                w = w && lds_ld(&slots[slot1(s, T)]) <= v;
+            win[m] = w;
+        }
+        if (EB != 0 && late) {
+#pragma unroll
+            for (int m = 0; m < BM; m++)
+                if (win[m]) {
+                    r_s[m].load(r.A, src[m]);
+                    r_h[m].load(r.A, tgt[m]);
                 }
-                src[m] = EMPTY;
+        }
+#pragma unroll
+        for (int m = 0; m < BM; m++) {
+            if (!win[m])
+                continue;
+            const uint32_t s = src[m], h = tgt[m];
+            if (EB != 0) {
+                r_h[m].store(r.A, s);
+                r_s[m].store(r.A, h);
+            } else {
+                pswap_generic(r.A, r.eb, s, h);
             }
+            src[m] = EMPTY;
         }
         cursor = cnew;
         rounds++;
@@ -392,7 +412,7 @@ __global__ __launch_bounds__(WGL) void rp_batch_kernel(BatchParams bp)
         uint64_t rounds = 0, attempts = 0;
         uint32_t status = 0;
         if (r.n > 1 && !r.invalid)
-            run_request<EB>(wg, r, (uint64_t)r.n + 64, &rounds, &attempts, &status);
+            run_request<EB>(wg, r, (uint64_t)r.n + 64, bp.late != 0, &rounds, &attempts, &status);
         attempts = sum_over_group_wg<S::WAVES>(attempts, sh_red);
         rounds = sum_over_group_wg<S::WAVES>(r.T == 0 ? rounds : (threadIdx.x == 0 ? rounds : 0),
                                              sh_red);
@@ -416,7 +436,7 @@ __global__ __launch_bounds__(WGL) void rp_batch_kernel(BatchParams bp)
         uint64_t rounds = 0, attempts = 0;
         uint32_t status = 0;
         if (r.n > 1 && !r.invalid)
-            run_request<EB>(wv, r, (uint64_t)r.n + 64, &rounds, &attempts, &status);
+            run_request<EB>(wv, r, (uint64_t)r.n + 64, bp.late != 0, &rounds, &attempts, &status);
         attempts = wave_sum64(attempts);
         rounds = wave_sum64(lane == 0 ? rounds : 0);
         if (lane == 0)
@@ -593,6 +613,7 @@ rp_batch_schedule default_schedule()
     s.table_ratio_x16 = (uint32_t)env_or("RP_BATCH_RATIO16", 16);
     s.workgroups_per_cu = (uint32_t)env_or("RP_BATCH_WPC", 4);
     s.workgroup_lanes = (uint32_t)env_or("RP_BATCH_LANES", 256);
+    s.late_loads = (uint32_t)env_or("RP_BATCH_LATE", 0);
     return s;
 }
 
@@ -702,6 +723,7 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
     bp.claims = claims;
     bp.res = b->res;
     bp.done_flags = b->done + 1;
+    bp.late = sched.late_loads ? 1u : 0u;
     if (count > 0) {
         hipLaunchKernelGGL(fn, dim3(grid), dim3(lanes), 0, stream, bp);
         if (hipGetLastError() != hipSuccess)
@@ -860,12 +882,14 @@ int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream
     rp_batch_schedule best = default_schedule();
     for (uint32_t c : cutoffs)
         for (uint32_t r16 : ratios)
-            for (const Shape_ &sh : shapes) {
+            for (const Shape_ &sh : shapes)
+              for (uint32_t late = 0; late < 2; late++) {
                 rp_batch_schedule s{};
                 s.wave_cutoff = c;
                 s.table_ratio_x16 = r16;
                 s.workgroups_per_cu = sh.wpc;
                 s.workgroup_lanes = sh.lanes;
+                s.late_loads = late;
                 float tot = 0.f;
                 bool ok = true;
                 for (int rep = 0; rep < 2 && ok; rep++) {

@@ -40,7 +40,11 @@ SCHEDULES = [None,
              {"wave_cutoff": 1 << 12, "table_ratio_x16": 24, "workgroups_per_cu": 2,
               "workgroup_lanes": 1024},
              {"wave_cutoff": 0, "table_ratio_x16": 16, "workgroups_per_cu": 1,
-              "workgroup_lanes": 1024}]
+              "workgroup_lanes": 1024},
+             {"wave_cutoff": 1 << 12, "table_ratio_x16": 24, "workgroups_per_cu": 4,
+              "late_loads": 1},
+             {"wave_cutoff": 1 << 10, "table_ratio_x16": 16, "workgroups_per_cu": 2,
+              "workgroup_lanes": 1024, "late_loads": 1}]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)

@@ -198,7 +198,7 @@ def _is_permutation(A, n):
 
 
 @pytest.mark.parametrize("dtype", [torch.int32, torch.int64])
-@pytest.mark.parametrize("eps", [0.25, 0.5])
+@pytest.mark.parametrize("eps", [0.25, 0.5, 0.75])
 def test_n2p28(dtype, eps):
     n, seed = 1 << 28, 1
     A = workloads.identity(n, dtype, DEV)
