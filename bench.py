@@ -27,6 +27,11 @@ paper's aux-space table: 0.4 %, 1 %, 2 %, 4 % of n, plus smaller bounds).
 pointer words each, the paper's list-contraction inputs) by in-place list
 contraction, at several auxiliary bounds, checked against the CPU oracle.
 
+`--workload scale` times the plain method at the other stated sizes: n = 2^28
+int32 and int64 at eps 0.25 / 0.5 / 0.75, n = 2^26 records of 64 bytes at
+eps 0.5, and n = 2^30 int64 at eps 0.2 / 0.25 / 1/3 / 0.5; each checked as a
+permutation with sampled positions against the CPU oracle.
+
 `--workload batch` measures the batched form instead: 4096 independent
 shuffles, n = floor(2^U) with U ~ Uniform[8, 20) drawn from a SplitMix64
 stream (seed 12345), int32 A[i] = i, instance seed 1000 + id, eps = 0.5, as
@@ -101,7 +106,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("plain", "batch", "serve", "ablation", "list"),
+    ap.add_argument("--workload",
+                    choices=("plain", "batch", "serve", "ablation", "list", "scale"),
                     default="plain")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve workload: seconds of arrivals per rate")
@@ -131,6 +137,8 @@ def main():
         run_ablation(args, log)
     elif args.workload == "list":
         run_list(args, log)
+    elif args.workload == "scale":
+        run_scale(args, log)
     else:
         run_plain(args, log)
 
@@ -216,10 +224,14 @@ def run_plain(args, log):
                    "k": stats["k"], "rounds": stats["rounds"],
                    "aux_words": stats["aux_words"],
                    "aux_bound_words": stats["aux_bound_words"],
-                   "grid": stats["grid"], "slots_per_lane": stats["slots_per_lane"]},
+                   "grid": stats["grid"], "slots_per_lane": stats["slots_per_lane"],
+                   "round_us": ms * 1e3 / max(1, stats["rounds"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
+                     "traffic_gbps": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_frac": (traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS)
+                     if traffic else None,
                      "kernel": "rp_rounds_kernel", "kernel_ms_events": ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "parity": parity,
@@ -688,6 +700,81 @@ def run_list(args, log):
                                "kind": "oracle",
                                "sample": "sequential walk of one random list of 1e7 elements"}
         log(f"cpu oracle: 1e7-element list walked in {dt:.2f} s")
+    print(json.dumps(out), flush=True)
+
+
+def run_scale(args, log):
+    """The plain method at the other stated sizes (module docstring)."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2103_01216_amd as rp
+    from paper_2103_01216_amd import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    cases = [("2^28 int32", 1 << 28, torch.int32, e) for e in (0.25, 0.5, 0.75)]
+    cases += [("2^28 int64", 1 << 28, torch.int64, e) for e in (0.25, 0.5, 0.75)]
+    cases += [("2^26 x 64 B records", 1 << 26, "rec64", 0.5)]
+    cases += [("2^30 int64", 1 << 30, torch.int64, e) for e in (0.2, 0.25, 1.0 / 3.0, 0.5)]
+    rows = []
+    A = None
+    for label, n, dt, eps in cases:
+        del A
+        torch.cuda.empty_cache()
+        A = workloads.records64(n, dev) if dt == "rec64" else workloads.identity(n, dt, dev)
+        eb = A.element_size() * (A.shape[1] if A.dim() > 1 else 1)
+        st = rp.rp_shuffle_inplace(A, seed=1, eps=eps, stream=stream).get()
+        key = A[:, 0] if A.dim() > 1 else A
+        seen = torch.zeros(n, dtype=torch.bool, device=dev)
+        seen[key.long()] = True
+        perm = bool(seen.all())
+        del seen
+        pos = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(3).integers(0, n, 256)]))
+        src = oracle.sample_sources(n, pos, seed=1)
+        got = key[torch.from_numpy(pos.astype(np.int64)).to(dev)].cpu().numpy()
+        exact = bool(np.array_equal(got.astype(np.int64), src.astype(np.int64)))
+        if not (perm and exact and st["status"] == 0):
+            log(f"PARITY FAILURE: {label} eps {eps}")
+            sys.exit(1)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            rp.rp_shuffle_inplace(A, seed=2 + i, eps=eps, stream=stream, stats=False)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        times = sorted(a.elapsed_time(b) for a, b in ev)
+        ms = times[len(times) // 2]
+        gbps = 4 * eb * n / (ms * 1e-3) / 1e9
+        rows.append({"case": label, "eps": eps, "ms_median": ms,
+                     "elements_per_s": n / (ms * 1e-3), "algorithmic_gbps": gbps,
+                     "frac_of_peak": gbps / HBM_PEAK_GBPS, "rounds": st["rounds"],
+                     "round_us": ms * 1e3 / max(1, st["rounds"]), "k": st["k"],
+                     "aux_words": st["aux_words"], "aux_bound_words": st["aux_bound_words"],
+                     "grid": st["grid"], "slots_per_lane": st["slots_per_lane"]})
+        log(f"{label} eps {eps:.3f}: {ms:.1f} ms, {n / (ms * 1e-3):.3g} el/s, {gbps:.0f} GB/s "
+            f"({100 * gbps / HBM_PEAK_GBPS:.2f} %), rounds {st['rounds']}, k {st['k']}, "
+            f"aux {st['aux_words']}/{st['aux_bound_words']}")
+    best = max(rows, key=lambda r: r["frac_of_peak"])
+    out = {
+        "metric": "in-place shuffle elements/s and % of HBM peak at the stated sizes",
+        "value": best["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": best["ms_median"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed",
+        "data": "synthetic",
+        "config": {"workload": "plain method at 2^28 int32/int64 x eps {0.25,0.5,0.75}, "
+                               "2^26 x 64 B records eps 0.5, 2^30 int64 x eps {0.2,0.25,1/3,0.5}",
+                   "cases": rows, "value_is": f"elements/s of {best['case']} eps {best['eps']:.3f}"},
+    }
     print(json.dumps(out), flush=True)
 
 
