@@ -32,13 +32,13 @@
 #include <vector>
 
 #include "rp.h"
+#include "rp_arena.h"
 
 namespace {
 
 constexpr int N_SMALL_STREAMS = 2;
 constexpr int N_LARGE_STREAMS = 2;
 constexpr int N_STREAMS = N_SMALL_STREAMS + N_LARGE_STREAMS;
-constexpr uint64_t ALIGN = 256;
 constexpr uint32_t PLAIN_AHEAD = 64;   // plain mode: requests enqueued ahead
 
 uint64_t now_ns()
@@ -47,81 +47,6 @@ uint64_t now_ns()
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
-
-// ---------------------------------------------------------------- arena
-
-// Best-fit allocator over one device region; free neighbours coalesce.
-class Arena {
-public:
-    void reset(uint64_t size)
-    {
-        size_ = size;
-        by_off_.clear();
-        by_len_.clear();
-        if (size)
-            insert(0, size);
-        in_use_ = peak_ = 0;
-    }
-    bool alloc(uint64_t bytes, uint64_t *off)
-    {
-        const uint64_t len = std::max<uint64_t>(ALIGN, (bytes + ALIGN - 1) / ALIGN * ALIGN);
-        auto it = by_len_.lower_bound({len, 0});
-        if (it == by_len_.end())
-            return false;
-        const uint64_t o = it->second, l = it->first;
-        erase(o, l);
-        if (l > len)
-            insert(o + len, l - len);
-        *off = o;
-        in_use_ += len;
-        peak_ = std::max(peak_, in_use_);
-        return true;
-    }
-    void free(uint64_t off, uint64_t bytes)
-    {
-        uint64_t len = std::max<uint64_t>(ALIGN, (bytes + ALIGN - 1) / ALIGN * ALIGN);
-        in_use_ -= len;
-        auto nx = by_off_.lower_bound(off);
-        if (nx != by_off_.end() && off + len == nx->first) {
-            const uint64_t o = nx->first, l = nx->second;
-            erase(o, l);
-            len += l;
-        }
-        auto pv = by_off_.lower_bound(off);
-        if (pv != by_off_.begin()) {
-            --pv;
-            if (pv->first + pv->second == off) {
-                const uint64_t o = pv->first, l = pv->second;
-                erase(o, l);
-                off = o;
-                len += l;
-            }
-        }
-        insert(off, len);
-    }
-    static uint64_t rounded(uint64_t bytes)
-    {
-        return std::max<uint64_t>(ALIGN, (bytes + ALIGN - 1) / ALIGN * ALIGN);
-    }
-    uint64_t in_use() const { return in_use_; }
-    uint64_t peak() const { return peak_; }
-    uint64_t size() const { return size_; }
-
-private:
-    void insert(uint64_t o, uint64_t l)
-    {
-        by_off_[o] = l;
-        by_len_.insert({l, o});
-    }
-    void erase(uint64_t o, uint64_t l)
-    {
-        by_off_.erase(o);
-        by_len_.erase({l, o});
-    }
-    uint64_t size_ = 0, in_use_ = 0, peak_ = 0;
-    std::map<uint64_t, uint64_t> by_off_;
-    std::set<std::pair<uint64_t, uint64_t>> by_len_;
-};
 
 // ------------------------------------------------------------- fill kernel
 
@@ -226,7 +151,7 @@ struct Server {
     rp_server_config cfg{};
     int device = 0;
     unsigned char *base = nullptr;
-    Arena arena;
+    rpserve::Arena arena;
     hipStream_t streams[N_STREAMS] = {};
     bool busy[N_STREAMS] = {};
     StreamBufs bufs[N_STREAMS];
@@ -704,7 +629,7 @@ int rp_server_create(const rp_server_config *cfg, uint64_t *server)
         destroy_server(s);
         return RP_ENOMEM;
     }
-    s->arena.reset(cfg->mem_budget_bytes / ALIGN * ALIGN);
+    s->arena.reset(cfg->mem_budget_bytes / rpserve::ALIGN * rpserve::ALIGN);
     for (int i = 0; i < N_STREAMS; i++)
         if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
             destroy_server(s);
@@ -723,7 +648,7 @@ int rp_server_submit(uint64_t server, const rp_server_request *req, uint64_t *ti
     if (s == nullptr || req == nullptr || ticket == nullptr || !valid_server_request(*req))
         return RP_EINVAL;
     const uint64_t bytes = req->n * req->elem_bytes;
-    if (Arena::rounded(bytes) > s->arena.size())
+    if (rpserve::Arena::rounded(bytes) > s->arena.size())
         return RP_EINVAL;
     {
         std::lock_guard<std::mutex> lk(s->mu);
