@@ -88,6 +88,7 @@ constexpr int WG = 256;                 // threads per workgroup
 constexpr int WAVES = WG / 64;
 constexpr uint32_t TAG_CYCLE = 256;     // rounds between full resets
 constexpr int MAXG = 2048;              // largest grid the gather supports
+constexpr int POLL = 4;                 // barrier flags a lane loads at once
 constexpr uint64_t WATCHDOG_TICKS = 500000000ull;  // 5 s at 100 MHz
 constexpr double TABLE_RATIO = 1.0;     // reservation slots per active swap
 
@@ -151,15 +152,23 @@ __device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t epoch,
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     bool ok = true;
     for (uint32_t sweep = 1; pending; sweep++) {
+        // Issue the loads of up to POLL flags before looking at any of them,
+        // so that a sweep costs about one load latency, not one per flag.
 #pragma unroll 1
-        for (int j = 0; j < nj; j++) {
-            if (!(pending & (1u << j)))
-                continue;
-            const uint32_t v = lane + 64u * j;
-            const uint64_t f = ld(&fl[v]);
-            if ((uint32_t)(f >> 48) == e16) {
-                pending &= ~(1u << j);
-                visit(v, f & ((1ull << 48) - 1));
+        for (int j0 = 0; j0 < nj; j0 += POLL) {
+            uint64_t f[POLL];
+#pragma unroll
+            for (int u = 0; u < POLL; u++) {
+                const int j = j0 + u;
+                f[u] = (j < nj && (pending & (1u << j))) ? ld(&fl[lane + 64u * j]) : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < POLL; u++) {
+                const int j = j0 + u;
+                if (j < nj && (pending & (1u << j)) && (uint32_t)(f[u] >> 48) == e16) {
+                    pending &= ~(1u << j);
+                    visit(lane + 64u * j, f[u] & ((1ull << 48) - 1));
+                }
             }
         }
         if (pending && (sweep & 63u) == 0) {

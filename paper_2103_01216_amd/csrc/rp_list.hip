@@ -48,6 +48,7 @@ constexpr int LWAVES = LWG / 64;
 constexpr int LM = 4;                       // block elements per lane
 constexpr uint32_t NILI = 0xFFFFFFFFu;
 constexpr uint32_t LMAXG = 2048;
+constexpr uint32_t LPOLL = 8;               // barrier flags a lane loads at once
 constexpr uint64_t LWATCHDOG = 500000000ull;  // 5 s at 100 MHz
 
 struct LParams {
@@ -89,9 +90,10 @@ __device__ __forceinline__ bool below(const LParams &p, uint64_t b1, uint32_t a,
 // workgroup's memory operations are complete (each wave waited for them, then
 // a workgroup barrier) before its flag is raised.  Returns the sum of the
 // payload fields (two 24-bit counts are summed independently) and false if
-// the watchdog fired or another workgroup reported an error.
+// the watchdog fired or another workgroup reported an error; *max_lo is the
+// largest low field.
 __device__ bool lgather(const LParams &p, uint32_t epoch, uint64_t payload, uint64_t *sum_lo,
-                        uint64_t *sum_hi)
+                        uint64_t *sum_hi, uint64_t *max_lo)
 {
     const uint32_t G = gridDim.x, lane = threadIdx.x & 63;
     const uint32_t e16 = epoch & 0xFFFFu;
@@ -99,41 +101,58 @@ __device__ bool lgather(const LParams &p, uint32_t epoch, uint64_t payload, uint
     if (lane == 0)
         st(&fl[blockIdx.x], ((uint64_t)e16 << 48) | payload);
     uint64_t lo = 0, hi = 0;
+    uint32_t mx = 0;
     bool ok = true;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    for (uint32_t v0 = 0; v0 < G; v0 += 64) {
-        const uint32_t v = v0 + lane;
-        if (v < G) {
-            for (uint32_t spin = 1;; spin++) {
-                const uint64_t f = ld(&fl[v]);
-                if ((uint32_t)(f >> 48) == e16) {
-                    lo += f & 0xFFFFFFull;
-                    hi += (f >> 24) & 0xFFFFFFull;
-                    break;
+    // The flags of lane l are l, l + 64, ...; every sweep loads all of its
+    // pending ones before checking any (one load latency per sweep).
+    const uint32_t nj = (G + 63u) / 64u;   // <= 32
+    uint32_t pending = 0;
+    for (uint32_t j = 0; j < nj; j++)
+        pending |= (lane + 64u * j < G) ? (1u << j) : 0u;
+    for (uint32_t sweep = 1; pending; sweep++) {
+#pragma unroll 1
+        for (uint32_t j0 = 0; j0 < nj; j0 += LPOLL) {
+            uint64_t f[LPOLL];
+#pragma unroll
+            for (uint32_t u = 0; u < LPOLL; u++) {
+                const uint32_t j = j0 + u;
+                f[u] = (j < nj && (pending & (1u << j))) ? ld(&fl[lane + 64u * j]) : 0ull;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < LPOLL; u++) {
+                const uint32_t j = j0 + u;
+                if (j < nj && (pending & (1u << j)) && (uint32_t)(f[u] >> 48) == e16) {
+                    pending &= ~(1u << j);
+                    lo += f[u] & 0xFFFFFFull;
+                    hi += (f[u] >> 24) & 0xFFFFFFull;
+                    mx = max(mx, (uint32_t)(f[u] & 0xFFFFFFull));
                 }
-                if ((spin & 63u) == 0 &&
-                    (__builtin_amdgcn_s_memrealtime() - t0 > LWATCHDOG || ld(p.err) != 0u)) {
-                    ok = false;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
             }
         }
-        if (!__all(ok))
+        if (pending && (sweep & 63u) == 0 &&
+            (__builtin_amdgcn_s_memrealtime() - t0 > LWATCHDOG || ld(p.err) != 0u)) {
+            ok = false;
             break;
+        }
+        if (pending)
+            __builtin_amdgcn_s_sleep(1);
     }
     *sum_lo = wave_sum64(lo);
     *sum_hi = wave_sum64(hi);
+    *max_lo = wave_max(mx);
     return __all(ok);
 }
 
-// Workgroup-wide: sum (lo, hi) over every lane of the grid; false on error.
+// Workgroup-wide: sum (lo, hi) over every lane of the grid -- or, with
+// take_max, the maximum of lo -- as wave-uniform values; false on error.
+// Every lane passes values below 2^24 / (lanes of the grid) for sums.
 __device__ bool grid_sum(const LParams &p, uint32_t *epoch, uint32_t lo, uint32_t hi,
-                         uint64_t *tot_lo, uint64_t *tot_hi, uint64_t *sh)
+                         uint64_t *tot_lo, uint64_t *tot_hi, uint64_t *sh, bool take_max = false)
 {
     __shared__ uint32_t s_lo[LWAVES], s_hi[LWAVES];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint64_t wl = wave_sum64(lo), wh = wave_sum64(hi);
+    const uint64_t wl = take_max ? wave_max(lo) : wave_sum64(lo), wh = wave_sum64(hi);
     if (lane == 0) {
         s_lo[wave] = (uint32_t)wl;
         s_hi[wave] = (uint32_t)wh;
@@ -144,12 +163,15 @@ __device__ bool grid_sum(const LParams &p, uint32_t *epoch, uint32_t lo, uint32_
     if (wave == 0) {
         uint64_t a = 0, b = 0;
         for (int i = 0; i < LWAVES; i++) {
-            a += s_lo[i];
+            a = take_max ? max(a, (uint64_t)s_lo[i]) : a + s_lo[i];
             b += s_hi[i];
         }
         bool ok = true;
         if (gridDim.x > 1) {
-            ok = lgather(p, *epoch, (b << 24) | a, &a, &b);
+            uint64_t m = 0;
+            ok = lgather(p, *epoch, (b << 24) | a, &a, &b, &m);
+            if (take_max)
+                a = m;
             if (!ok && lane == 0)
                 st(p.err, 1u);
         }
@@ -287,63 +309,10 @@ __global__ __launch_bounds__(LWG) void rp_list_kernel(LParams p)
                 }
             }
         }
-        // rounds of this block = max over its elements (a grid-wide max via
-        // a 24-bit count of "elements at or above each round" is not needed:
-        // carry max + 1 through the barrier's low field as a maximum)
-        __shared__ uint32_t s_max[LWAVES];
-        const uint32_t wmax = wave_max(mymax);
-        if ((t & 63) == 0)
-            s_max[t >> 6] = wmax;
-        wait_mem();
-        __syncthreads();
-        ++epoch;
-        if ((t >> 6) == 0) {
-            uint32_t a = 0;
-            for (int i = 0; i < LWAVES; i++)
-                a = max(a, s_max[i]);
-            bool ok = true;
-            if (G > 1) {
-                // maximum over workgroups: the payload is a single value;
-                // read every flag and take the largest
-                const uint32_t e16 = epoch & 0xFFFFu;
-                uint64_t *fl = p.flags + (uint64_t)(epoch & 1u) * G;
-                if ((t & 63) == 0)
-                    st(&fl[w], ((uint64_t)e16 << 48) | a);
-                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-                uint32_t mx = 0;
-                for (uint32_t v0 = 0; v0 < G && ok; v0 += 64) {
-                    const uint32_t v = v0 + (t & 63);
-                    if (v < G) {
-                        for (uint32_t spin = 1;; spin++) {
-                            const uint64_t f = ld(&fl[v]);
-                            if ((uint32_t)(f >> 48) == e16) {
-                                mx = max(mx, (uint32_t)(f & 0xFFFFFFull));
-                                break;
-                            }
-                            if ((spin & 63u) == 0 &&
-                                (__builtin_amdgcn_s_memrealtime() - t0 > LWATCHDOG ||
-                                 ld(p.err) != 0u)) {
-                                ok = false;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
-                    }
-                    ok = __all(ok);
-                }
-                a = wave_max(mx);
-                if (!ok && (t & 63) == 0)
-                    st(p.err, 1u);
-            }
-            if ((t & 63) == 0) {
-                sh[0] = a;
-                sh[2] = ok ? 0u : 1u;
-            }
-        }
-        __syncthreads();
-        if (__builtin_amdgcn_readfirstlane((uint32_t)sh[2]))
+        // rounds of this block = the largest (round + 1) over its elements
+        if (!grid_sum(p, &epoch, mymax, 0, &lo, &hi, sh, true))
             return;
-        const uint32_t R = __builtin_amdgcn_readfirstlane((uint32_t)sh[0]);
+        const uint32_t R = (uint32_t)lo;
         for (uint32_t r = R; r-- > 0;) {
 #pragma unroll
             for (int m = 0; m < LM; m++)
