@@ -406,7 +406,8 @@ def _replay(rp, mode, arrivals, sizes, seeds, log, drain_s):
     """Submit each request at its arrival time; collect completion times.
     Returns (latencies_s, completed_elements, span_s, unfinished)."""
     import threading
-    srv = rp.Server(SERVE["budget"], mode=mode, auto_release=True)
+    srv = rp.Server(SERVE["budget"], mode=mode, auto_release=True,
+                    large_alone=(mode == rp.RP_SERVE_BATCHED))
     tickets = {}
     lat = {}
     stop = threading.Event()

@@ -93,9 +93,10 @@ uint64_t rp_aux_bound_words(uint64_t n, double eps);
  * Plan a call without running it (host only, no GPU): fills *stats_out
  * (host) with the k, aux_words, aux_bound_words, grid, slots_per_lane and
  * table_slots that rp_shuffle_inplace would use on device `device` for these
- * arguments; the other fields are zero.  Returns RP_OK, RP_EINVAL or
- * RP_ENOMEM (bound too small for even one active swap).  device < 0 assumes
- * an MI355X with 256 compute units.
+ * arguments; the other fields are zero.  Returns RP_OK, RP_EINVAL, or
+ * RP_EDEVICE when `device` cannot be queried.  A bound too small for even the
+ * smallest table gives k = 1 (one active swap: the sequential loop, which
+ * needs one word).  device < 0 assumes an MI355X with 256 compute units.
  */
 int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
             rp_stats *stats_out);
@@ -334,7 +335,12 @@ typedef struct rp_server_config {
     uint32_t tick_us;            /* dispatcher poll interval; 0: 50 */
     uint32_t auto_release;       /* 1: free each array as soon as it is done
                                     (results are not kept) */
-    uint32_t reserved;           /* 0 */
+    uint32_t large_alone;        /* 1: run large requests one at a time, in
+                                    arrival order, each alone with
+                                    rp_shuffle_inplace (every compute unit
+                                    works on it) instead of in one workgroup
+                                    of a batched launch; when more than 4
+                                    wait, batch them */
     rp_batch_schedule schedule;  /* all zero: the tuned or default schedule */
 } rp_server_config;
 

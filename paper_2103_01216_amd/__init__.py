@@ -371,7 +371,7 @@ class rp_server_config(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("mode", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("large_log2", ctypes.c_uint32),
                 ("tick_us", ctypes.c_uint32), ("auto_release", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("schedule", rp_batch_schedule)]
+                ("large_alone", ctypes.c_uint32), ("schedule", rp_batch_schedule)]
 
 
 class rp_server_request(ctypes.Structure):
@@ -420,7 +420,8 @@ class Server:
 
     def __init__(self, mem_budget_bytes: int, *, mode: int = RP_SERVE_BATCHED,
                  max_batch: int = 0, large_log2: int = 0, tick_us: int = 0,
-                 auto_release: bool = False, schedule: dict | None = None):
+                 auto_release: bool = False, large_alone: bool = False,
+                 schedule: dict | None = None):
         cfg = rp_server_config()
         cfg.mem_budget_bytes = int(mem_budget_bytes)
         cfg.mode = mode
@@ -428,6 +429,7 @@ class Server:
         cfg.large_log2 = large_log2
         cfg.tick_us = tick_us
         cfg.auto_release = 1 if auto_release else 0
+        cfg.large_alone = 1 if large_alone else 0
         if schedule:
             cfg.schedule = _schedule_struct(schedule)
         h = ctypes.c_uint64(0)

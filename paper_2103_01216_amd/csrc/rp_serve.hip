@@ -40,6 +40,7 @@ constexpr int N_SMALL_STREAMS = 2;
 constexpr int N_LARGE_STREAMS = 2;
 constexpr int N_STREAMS = N_SMALL_STREAMS + N_LARGE_STREAMS;
 constexpr uint32_t PLAIN_AHEAD = 64;   // plain mode: requests enqueued ahead
+constexpr size_t ALONE_QUEUE = 4;      // large_alone: batch beyond this many waiting
 
 uint64_t now_ns()
 {
@@ -295,7 +296,7 @@ bool reap(Server &s)
     for (size_t li = 0; li < s.inflight.size();) {
         Launch &L = s.inflight[li];
         bool finished = false;
-        if (s.cfg.mode == RP_SERVE_PLAIN) {
+        if (L.done_ev) {   // one rp_shuffle_inplace call (plain mode, or alone)
             const hipError_t e = hipEventQuery(L.done_ev);
             if (e == hipSuccess || e != hipErrorNotReady) {
                 std::lock_guard<std::mutex> lk(s.mu);
@@ -435,13 +436,60 @@ int free_stream(const Server &s, int cls)
     return -1;
 }
 
+// One admitted large request alone on stream `si`, with the single-instance
+// kernel: all compute units work on it (its rounds are grid-wide) instead of
+// one workgroup.  Completion is an event recorded after the call.
+int launch_alone(Server &s, int si)
+{
+    std::vector<Req *> rs;
+    const std::vector<uint64_t> tickets = take_admitted(s, 1, 1, &rs);
+    if (tickets.empty())
+        return RP_PENDING;
+    hipStream_t st = s.streams[si];
+    Launch P;
+    P.stream = si;
+    P.tickets = tickets;
+    int rc = fill_arrays(s, si, rs);
+    if (rc == RP_OK)
+        rc = rp_shuffle_inplace(s.base + rs[0]->off, rs[0]->q.n, rs[0]->q.elem_bytes, nullptr,
+                                rs[0]->q.seed, rs[0]->q.eps, st, nullptr);
+    if (rc == RP_OK && (hipEventCreateWithFlags(&P.done_ev, hipEventDisableTiming) != hipSuccess ||
+                        hipEventRecord(P.done_ev, st) != hipSuccess))
+        rc = RP_EDEVICE;
+    if (rc != RP_OK) {
+        if (P.done_ev)
+            (void)hipEventDestroy(P.done_ev);
+        fail_tickets(s, tickets, rc);
+        return rc;
+    }
+    s.busy[si] = true;
+    s.inflight.push_back(P);
+    return RP_OK;
+}
+
 // Batched mode: every admitted request of class `cls` in one launch on a
-// free stream of that class.
+// free stream of that class (or, with large_alone, a single large request
+// that arrives while no other large one runs goes out alone).
 int launch_batched(Server &s, int cls)
 {
     const int si = free_stream(s, cls);
     if (si < 0)
         return RP_PENDING;
+    if (cls == 1 && s.cfg.large_alone) {
+        // Large requests run alone, one after another in arrival order, as
+        // long as few of them wait; a longer queue (overload) goes out as one
+        // batched launch so that they progress side by side.
+        bool alone_running = false;
+        for (const Launch &L : s.inflight)
+            alone_running = alone_running || (L.done_ev && L.stream >= N_SMALL_STREAMS);
+        size_t waiting;
+        {
+            std::lock_guard<std::mutex> lk(s.mu);
+            waiting = s.admitted[1].size();
+        }
+        if (waiting <= ALONE_QUEUE)
+            return alone_running ? RP_PENDING : launch_alone(s, si);
+    }
     std::vector<Req *> rs;
     const std::vector<uint64_t> tickets =
         take_admitted(s, cls, s.cfg.max_batch ? s.cfg.max_batch : SIZE_MAX, &rs);

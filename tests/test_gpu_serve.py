@@ -106,10 +106,11 @@ def test_admission_respects_budget():
     assert st["peak_bytes"] >= 2 * sizes[0] * 8
 
 
-def test_large_requests_and_record_sizes():
+@pytest.mark.parametrize("large_alone", [False, True])
+def test_large_requests_and_record_sizes(large_alone):
     reqs = [((1 << 22) + 5, 8, 71), ((1 << 23) + 1, 4, 72), (3000, 8, 73),
             (5000, 16, 74), (70000, 4, 75)]
-    with rp.Server(1 << 30, large_log2=22) as srv:
+    with rp.Server(1 << 30, large_log2=22, large_alone=large_alone) as srv:
         tickets = [srv.submit(n, eb, s) for n, eb, s in reqs]
         _wait_all(srv, tickets)
         for t, (n, eb, s) in zip(tickets, reqs):
@@ -156,3 +157,23 @@ def test_rejections_and_auto_release():
             assert info["state"] == rp.RP_REQ_DONE and info["A"] is None
             assert srv.release(t)
         assert srv.stats()["bytes_in_use"] == 0
+
+
+def test_large_alone_in_a_mix():
+    """Large requests that run alone on the whole GPU while small ones keep
+    arriving: every result is still the request's own shuffle."""
+    rng = np.random.default_rng(17)
+    sizes = [int(x) for x in workloads.batch_sizes(60, 10, 24, 33)]
+    seeds = [5 * 10**5 + i for i in range(len(sizes))]
+    gaps = rng.exponential(1.0 / 300.0, size=len(sizes))
+    with rp.Server(4 << 30, large_log2=21, large_alone=True) as srv:
+        tickets = []
+        for n, sd, g in zip(sizes, seeds, gaps):
+            time.sleep(float(g))
+            tickets.append(srv.submit(n, 8, sd))
+        _wait_all(srv, tickets, timeout=120)
+        for t, n, sd in zip(tickets, sizes, seeds):
+            info = srv.info(t)
+            assert info["status"] == 0
+            _check_exact(_result(srv, t, n, 8), n, sd, 8)
+            assert srv.release(t)
