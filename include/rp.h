@@ -327,7 +327,8 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
 
 typedef struct rp_server_config {
     uint64_t mem_budget_bytes;   /* arena size: bound on the bytes of all
-                                    admitted, unreleased arrays */
+                                    admitted, unreleased arrays; 0: the
+                                    process default (rp_set_mem_budget) */
     uint32_t mode;               /* RP_SERVE_BATCHED or RP_SERVE_PLAIN */
     uint32_t max_batch;          /* requests per launch; 0: no limit */
     uint32_t large_log2;         /* n >= 2^large_log2 uses the large-request
@@ -374,6 +375,11 @@ typedef struct rp_server_stats {
     uint64_t peak_bytes;         /* maximum of bytes_in_use so far */
     uint64_t elements_done;      /* sum of n over finished requests */
 } rp_server_stats;
+
+/* Process-wide default admission budget (bytes of device memory for request
+ * arrays) of servers created with mem_budget_bytes = 0.  Host only.  The
+ * initial default is 64 GiB.  RP_EINVAL for 0. */
+int rp_set_mem_budget(uint64_t bytes);
 
 /* Create a server on the current device: allocates the arena and starts the
  * dispatcher thread.  *server (host) receives its handle.  RP_EINVAL for a bad

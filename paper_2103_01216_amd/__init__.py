@@ -415,8 +415,19 @@ def _server_lib():
     return L
 
 
+def rp_set_mem_budget(nbytes: int) -> None:
+    """Default admission budget of servers created with budget 0."""
+    L = _server_lib()
+    L.rp_set_mem_budget.restype = ctypes.c_int
+    L.rp_set_mem_budget.argtypes = [ctypes.c_uint64]
+    rc = L.rp_set_mem_budget(int(nbytes))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_set_mem_budget")
+
+
 class Server:
-    """A request loop on the current device (rp_server_* of include/rp.h)."""
+    """A request loop on the current device (rp_server_* of include/rp.h).
+    mem_budget_bytes = 0 takes the default set by rp_set_mem_budget."""
 
     def __init__(self, mem_budget_bytes: int, *, mode: int = RP_SERVE_BATCHED,
                  max_batch: int = 0, large_log2: int = 0, tick_us: int = 0,

@@ -264,6 +264,12 @@ __global__ __launch_bounds__(LWG) void rp_list_kernel(LParams p)
             // Splice: i's left neighbour L and right neighbour R are not
             // spliced this round (their keys are higher), and no other
             // spliced element touches the words written here.
+            // (all weight loads first, then the stores: one load latency)
+            uint32_t wls[LM];
+#pragma unroll
+            for (int m = 0; m < LM; m++)
+                wls[m] = go[m] ? (uint32_t)(ld(&p.rec[2 * (uint64_t)(uint32_t)pw[m] + 1]) >> 32)
+                               : 0u;
 #pragma unroll
             for (int m = 0; m < LM; m++) {
                 if (!go[m])
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(LWG) void rp_list_kernel(LParams p)
                 const uint64_t i = idx[m];
                 const uint32_t L = (uint32_t)pw[m], R = (uint32_t)nw[m];
                 const uint64_t wi = nw[m] >> 32;
-                const uint64_t wl = ld(&p.rec[2 * (uint64_t)L + 1]) >> 32;
+                const uint64_t wl = wls[m];
                 st64(&p.rec[2 * (uint64_t)L + 1], (uint64_t)R | ((wl + wi) << 32));
                 if (R != NILI)
                     st64(&p.rec[2 * (uint64_t)R], (uint64_t)L);
@@ -314,10 +320,14 @@ __global__ __launch_bounds__(LWG) void rp_list_kernel(LParams p)
             return;
         const uint32_t R = (uint32_t)lo;
         for (uint32_t r = R; r-- > 0;) {
+            uint64_t lr[LM];
+#pragma unroll
+            for (int m = 0; m < LM; m++)
+                lr[m] = rr[m] == r ? ld(&p.rank[left[m]]) : 0ull;
 #pragma unroll
             for (int m = 0; m < LM; m++)
                 if (rr[m] == r)
-                    st64(&p.rank[idx[m]], ld(&p.rank[left[m]]) + off[m]);
+                    st64(&p.rank[idx[m]], lr[m] + off[m]);
             if (!grid_sum(p, &epoch, 0, 0, &lo, &hi, sh))
                 return;
             rrounds++;

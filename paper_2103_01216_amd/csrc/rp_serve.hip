@@ -175,6 +175,7 @@ struct Server {
 std::mutex g_smu;
 std::map<uint64_t, Server *> g_servers;
 uint64_t g_next_server = 1;
+uint64_t g_default_budget = 64ull << 30;   // guarded by g_smu
 
 Server *find_server(uint64_t id)
 {
@@ -658,26 +659,39 @@ void destroy_server(Server *s)
 
 extern "C" {
 
+int rp_set_mem_budget(uint64_t bytes)
+{
+    if (bytes == 0)
+        return RP_EINVAL;
+    std::lock_guard<std::mutex> lk(g_smu);
+    g_default_budget = bytes;
+    return RP_OK;
+}
+
 int rp_server_create(const rp_server_config *cfg, uint64_t *server)
 {
-    if (cfg == nullptr || server == nullptr || cfg->mem_budget_bytes == 0 ||
+    if (cfg == nullptr || server == nullptr ||
         (cfg->mode != RP_SERVE_BATCHED && cfg->mode != RP_SERVE_PLAIN) || cfg->large_log2 > 40)
         return RP_EINVAL;
     Server *s = new Server;
     s->cfg = *cfg;
+    if (s->cfg.mem_budget_bytes == 0) {
+        std::lock_guard<std::mutex> lk(g_smu);
+        s->cfg.mem_budget_bytes = g_default_budget;
+    }
     if (s->cfg.large_log2 == 0)
         s->cfg.large_log2 = 22;
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return RP_EDEVICE;
     }
-    if (hipMalloc(reinterpret_cast<void **>(&s->base), cfg->mem_budget_bytes) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void **>(&s->base), s->cfg.mem_budget_bytes) != hipSuccess) {
         (void)hipGetLastError();
         s->base = nullptr;
         destroy_server(s);
         return RP_ENOMEM;
     }
-    s->arena.reset(cfg->mem_budget_bytes / rpserve::ALIGN * rpserve::ALIGN);
+    s->arena.reset(s->cfg.mem_budget_bytes / rpserve::ALIGN * rpserve::ALIGN);
     for (int i = 0; i < N_STREAMS; i++)
         if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
             destroy_server(s);

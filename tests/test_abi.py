@@ -124,3 +124,11 @@ def test_variant_rejects_unknown():
     assert L.rp_shuffle_variant(None, 0, 8, None, 0, 0.5, 7, None, None) == rp.RP_EINVAL
     assert L.rp_shuffle_variant(None, 0, 8, None, 0, 0.5, -1, None, None) == rp.RP_EINVAL
     assert L.rp_shuffle_variant(None, 0, 8, None, 0, 1.5, 0, None, None) == rp.RP_EINVAL
+
+
+def test_set_mem_budget_host_only():
+    L = rp.lib()
+    L.rp_set_mem_budget.restype = ctypes.c_int
+    L.rp_set_mem_budget.argtypes = [ctypes.c_uint64]
+    assert L.rp_set_mem_budget(0) == rp.RP_EINVAL
+    assert L.rp_set_mem_budget(64 << 30) == rp.RP_OK

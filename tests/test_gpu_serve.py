@@ -177,3 +177,17 @@ def test_large_alone_in_a_mix():
             assert info["status"] == 0
             _check_exact(_result(srv, t, n, 8), n, sd, 8)
             assert srv.release(t)
+
+
+def test_default_budget():
+    rp.rp_set_mem_budget(64 << 20)
+    try:
+        with rp.Server(0) as srv:
+            with pytest.raises(rp.RpError):
+                srv.submit((64 << 20) // 8 + 1, 8, 1)     # larger than the default arena
+            t = srv.submit(1000, 8, 2)
+            _wait_all(srv, [t])
+            _check_exact(_result(srv, t, 1000, 8), 1000, 2, 8)
+            assert srv.release(t)
+    finally:
+        rp.rp_set_mem_budget(64 << 30)
