@@ -89,6 +89,7 @@ constexpr int WAVES = WG / 64;
 constexpr uint32_t TAG_CYCLE = 256;     // rounds between full resets
 constexpr int MAXG = 2048;              // largest grid the gather supports
 constexpr int POLL = 4;                 // barrier flags a lane loads at once
+constexpr uint32_t LDS_TAB_BYTES = 65536;  // largest LDS table of such a launch
 constexpr uint64_t WATCHDOG_TICKS = 500000000ull;  // 5 s at 100 MHz
 constexpr double TABLE_RATIO = 1.0;     // reservation slots per active swap
 
@@ -110,7 +111,7 @@ struct Params {
     uint64_t *dstats;    // rp_stats laid out as 12 x 64-bit words
     uint64_t max_rounds;
     uint32_t variant;    // RP_VARIANT_*: how reservations are held and checked
-    uint32_t pad;
+    uint32_t lds_tab;    // 1: the launch uses the LDS variant of the kernel
     uint64_t *R64;       // RP_VARIANT_LINEAR: one priority word per position
 };
 
@@ -206,8 +207,9 @@ __device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t epoch,
 }
 
 // M: swap slots per lane.  EB: record size held in registers (4, 8, 16), or
-// 0 for any multiple of 4 up to 256 bytes, moved after the decision.
-template <int M, int EB>
+// 0 for any multiple of 4 up to 256 bytes, moved after the decision.  LDS: a
+// one-workgroup launch whose slot array and window live in dynamic LDS.
+template <int M, int EB, bool LDS>
 __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 {
     __shared__ uint32_t sh_wave[WAVES];
@@ -222,6 +224,19 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
     const uint32_t W = p.variant == RP_VARIANT_FINAL ? p.bmw * 32u : 0u;
     const bool linear = p.variant == RP_VARIANT_LINEAR;
     const bool twores = p.variant == RP_VARIANT_TWORES;
+
+    // A one-workgroup launch keeps its slot array and window in LDS (the
+    // same words, on chip): its rounds are then workgroup barriers and LDS
+    // atomics.
+    uint32_t *slots = p.slots, *bm = p.bm;
+    if constexpr (LDS) {
+        extern __shared__ uint32_t dyn_lds[];
+        slots = dyn_lds;
+        bm = dyn_lds + p.T;
+        for (uint32_t i = t; i < p.T + 2 * p.bmw; i += WG)
+            dyn_lds[i] = 0u;
+        __syncthreads();
+    }
 
     uint32_t src[M], tgt[M];
     bool usable[M];
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
         // extra barrier, so that tags restart from 0 over an empty array.
         if (tag == 0 && rounds > 0 && !linear) {
             for (uint32_t i = w * WG + t; i < p.T; i += G * WG)
-                clear_rmw(&p.slots[i]);
+                clear_rmw(&slots[i]);
             if (!plain_barrier(p, ++epoch, sh_res)) {
                 failed = true;
                 break;
@@ -378,17 +393,17 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                     continue;
                 }
                 const uint32_t v = (tag << RANKB) | (src[m] - cnew);
-                __hip_atomic_fetch_max(&p.slots[slot1(tgt[m], p.T)], v,
+                __hip_atomic_fetch_max(&slots[slot1(tgt[m], p.T)], v,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (p.choices > 1)
-                    __hip_atomic_fetch_max(&p.slots[slot2(tgt[m], p.T)], v,
+                    __hip_atomic_fetch_max(&slots[slot2(tgt[m], p.T)], v,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (twores)
-                    __hip_atomic_fetch_max(&p.slots[slot1(src[m], p.T)], v,
+                    __hip_atomic_fetch_max(&slots[slot1(src[m], p.T)], v,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t d = tgt[m] - cnew;
                 if (tgt[m] >= cnew && d < W)
-                    __hip_atomic_fetch_or(&p.bm[(uint64_t)par * p.bmw + (d >> 5)],
+                    __hip_atomic_fetch_or(&bm[(uint64_t)par * p.bmw + (d >> 5)],
                                           1u << (d & 31u), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -396,7 +411,7 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
         {
             const uint32_t op = par ^ 1u;
             for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
-                clear_rmw(&p.bm[(uint64_t)op * p.bmw + i]);
+                clear_rmw(&bm[(uint64_t)op * p.bmw + i]);
         }
         attempts += act;
 
@@ -454,13 +469,13 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                 q2[m] = (uint32_t)(b >> 32);
                 continue;
             }
-            t1[m] = ld(&p.slots[slot1(h, p.T)]);
-            t2[m] = (p.choices > 1) ? ld(&p.slots[slot2(h, p.T)]) : 0u;
+            t1[m] = ld(&slots[slot1(h, p.T)]);
+            t2[m] = (p.choices > 1) ? ld(&slots[slot2(h, p.T)]) : 0u;
             if (ds < W) {
-                q1[m] = ld(&p.bm[(uint64_t)par * p.bmw + (ds >> 5)]);
+                q1[m] = ld(&bm[(uint64_t)par * p.bmw + (ds >> 5)]);
             } else {
-                q1[m] = ld(&p.slots[slot1(s, p.T)]);
-                q2[m] = (p.choices > 1) ? ld(&p.slots[slot2(s, p.T)]) : 0u;
+                q1[m] = ld(&slots[slot1(s, p.T)]);
+                q2[m] = (p.choices > 1) ? ld(&slots[slot2(s, p.T)]) : 0u;
             }
         }
 #pragma unroll
@@ -592,6 +607,7 @@ __global__ void rp_seed_targets_kernel(const uint64_t *idx, uint64_t count,
 
 struct Plan {
     bool single;      // k = 1 path
+    bool lds;         // one workgroup: slots and window in dynamic LDS
     uint32_t G, M, k, T, bmw;
     uint64_t bound, aux_bytes;
     int eb_class;     // 4, 8, 16 or 0
@@ -711,6 +727,7 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
     pl->M = (uint32_t)M;
     pl->T = (uint32_t)T;
     pl->bmw = (uint32_t)bmw;
+    pl->lds = G == 1 && M == 1 && (T + 2 * bmw) * 4 <= LDS_TAB_BYTES;
     return RP_OK;
 }
 
@@ -733,10 +750,21 @@ template <int M>
 KernelFn pick_eb(int ebc)
 {
     switch (ebc) {
-    case 4: return rp_rounds_kernel<M, 4>;
-    case 8: return rp_rounds_kernel<M, 8>;
-    case 16: return rp_rounds_kernel<M, 16>;
-    default: return rp_rounds_kernel<M, 0>;
+    case 4: return rp_rounds_kernel<M, 4, false>;
+    case 8: return rp_rounds_kernel<M, 8, false>;
+    case 16: return rp_rounds_kernel<M, 16, false>;
+    default: return rp_rounds_kernel<M, 0, false>;
+    }
+}
+
+// One workgroup, one slot per lane, tables in LDS.
+KernelFn pick_lds_kernel(int ebc)
+{
+    switch (ebc) {
+    case 4: return rp_rounds_kernel<1, 4, true>;
+    case 8: return rp_rounds_kernel<1, 8, true>;
+    case 16: return rp_rounds_kernel<1, 16, true>;
+    default: return rp_rounds_kernel<1, 0, true>;
     }
 }
 
@@ -917,6 +945,7 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
                     ? (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)))
                     : 1u;
     p.variant = (uint32_t)variant;
+    p.lds_tab = (variant != RP_VARIANT_LINEAR && pl.lds) ? 1u : 0u;
     p.hoist = env_int("RP_HOIST", 1) ? 1u : 0u;
     p.bmw = pl.bmw;
     p.dstats = dstats;
@@ -967,10 +996,11 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
             return RP_EDEVICE;
         }
     } else {
-        KernelFn fn = pick_kernel((int)pl.M, pl.eb_class);
+        KernelFn fn = p.lds_tab ? pick_lds_kernel(pl.eb_class) : pick_kernel((int)pl.M, pl.eb_class);
         void *args[] = {&p};
+        const size_t lds_bytes = p.lds_tab ? ((size_t)pl.T + 2 * (size_t)pl.bmw) * 4 : 0;
         if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(pl.G),
-                                       dim3(WG), args, 0, stream) != hipSuccess) {
+                                       dim3(WG), args, lds_bytes, stream) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFreeAsync(mem, stream);
             return RP_EDEVICE;
