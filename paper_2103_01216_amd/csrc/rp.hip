@@ -24,27 +24,29 @@
 //               removes them; a swap with H[s] = s is a no-op); both records
 //               of every active swap are read;
 //   3. reserve  the priority write of Algorithm 1 on R[H[s]], into a hashed
-//               reservation array: R[x] is replaced by two slots
-//               R'[h1(x)], R'[h2(x)] of an O(k)-word array, each updated with
-//               an atomic max of the swap's priority; bit H[s] of the dense
-//               window is set when H[s] lies in it;
+//               reservation array: R[x] is replaced by the slot R'[h1(x)] of
+//               an O(k)-word array (or two slots h1, h2 when two choices are
+//               asked for), updated with an atomic max of the swap's
+//               priority; bit H[s] of the dense window is set when H[s] lies
+//               in it;
 //   4. barrier
-//   5. commit   swap s wins iff it is still the maximum in one of its two
-//               slots (so no active swap with a larger source, i.e. earlier
+//   5. commit   swap s wins iff it is still the maximum in a slot of key
+//               H[s] (so no active swap with a larger source, i.e. earlier
 //               in the sequential order, targets H[s]) and no active swap
-//               targets s (dense window bit; the two slots of key s for the
-//               rare source outside the window) -- the single-reservation
-//               test of Appendix A.2.  Winners swap A[s] and A[H[s]]; losers
-//               stay in their slots for the next round (the paper's pack step
-//               becomes the per-workgroup prefix sum over free slots in
-//               step 1).
+//               targets s (dense window bit; the slot of key s for the rare
+//               source outside the window) -- the single-reservation test of
+//               Appendix A.2.  Winners swap A[s] and A[H[s]]; losers stay in
+//               their slots for the next round (the paper's pack step becomes
+//               the per-workgroup prefix sum over free slots in step 1).
 //
 // Why the hashed array is exact: a slot holds the maximum priority over all
 // keys that hash to it, so "s is the maximum in a slot of key x" implies that
-// no active swap with higher priority reserved x (it would have raised both
-// of x's slots).  Collisions between different keys can only make a swap lose
-// a round it could have won (it retries next round; the top unfinished swap
-// is the maximum everywhere and always commits), never win wrongly.
+// no active swap with higher priority reserved x (it would have raised every
+// slot of x).  Collisions between different keys can only make a swap lose a
+// round it could have won (it retries next round; the top unfinished swap is
+// the maximum everywhere and always commits), never win wrongly.  The array
+// has about one slot per active swap when the bound limits k, and up to four
+// when the grid does and the bound leaves words to spare.
 //
 // Priorities are (tag:8 | rank:24) with rank = s - cursor_new and tag = round
 // number mod 256, so values written in later rounds are larger and the array
@@ -53,7 +55,8 @@
 // 2^24.  The dense window is double-buffered by round parity and the stale
 // parity is cleared during step 3: the cleaning phase of Appendix A.1.
 //
-// Auxiliary layout (device memory, every byte counted against the bound):
+// Auxiliary layout (device memory, or LDS for the slot array and window of a
+// one-workgroup launch; every byte counted against the bound):
 //   slots[T]            hashed reservation array, 32-bit priorities
 //   bm[par * bmw + i]   dense window: bit x set iff an active swap targets
 //                       cursor_new + x, for x < 32 * bmw (at least 2k)
@@ -92,6 +95,7 @@ constexpr int POLL = 4;                 // barrier flags a lane loads at once
 constexpr uint32_t LDS_TAB_BYTES = 65536;  // largest LDS table of such a launch
 constexpr uint64_t WATCHDOG_TICKS = 500000000ull;  // 5 s at 100 MHz
 constexpr double TABLE_RATIO = 1.0;     // reservation slots per active swap
+constexpr double SPARE_RATIO_MAX = 4.0; // the most when spare words allow more
 
 struct Params {
     unsigned char *A;
@@ -620,10 +624,12 @@ double table_ratio()
     return (r > 0.05 && r < 64.0) ? r : TABLE_RATIO;
 }
 
-// Device bytes the rounds path allocates for k active swaps on G workgroups.
-uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_out)
+// Device bytes the rounds path allocates for k active swaps on G workgroups,
+// with `ratio` reservation slots per active swap.
+uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_out,
+                       double ratio = table_ratio())
 {
-    const uint64_t T = std::max<uint64_t>(2, (uint64_t)std::ceil(table_ratio() * (double)k));
+    const uint64_t T = std::max<uint64_t>(2, (uint64_t)std::ceil(ratio * (double)k));
     const uint64_t bmw = std::max<uint64_t>(1, (2 * k + 31) / 32);
     if (T_out) *T_out = T;
     if (bmw_out) *bmw_out = bmw;
@@ -720,8 +726,23 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
         pl->aux_bytes = 8;
         return RP_OK;
     }
+    // When the grid rather than the bound caps k, the spare words go to a
+    // sparser reservation array: with r slots per swap a swap loses to a
+    // collision with probability about 1 - r(1 - e^(-1/r)) (37 % at r = 1,
+    // 12 % at r = 4), and every such loss costs another round's atomic and
+    // record reads.
+    double ratio = table_ratio();
+    const char *fixed = getenv("RP_TABLE_RATIO");
+    if (!(fixed && *fixed) && k < kmax_for(G)) {
+        for (const double r : {SPARE_RATIO_MAX, 3.0, 2.0, 1.5, 1.25}) {
+            if (r > ratio && aux_bytes_for(k, G, nullptr, nullptr, r) <= budget) {
+                ratio = r;
+                break;
+            }
+        }
+    }
     uint64_t T, bmw;
-    pl->aux_bytes = aux_bytes_for(k, G, &T, &bmw);
+    pl->aux_bytes = aux_bytes_for(k, G, &T, &bmw, ratio);
     pl->k = (uint32_t)k;
     pl->G = (uint32_t)G;
     pl->M = (uint32_t)M;
@@ -913,7 +934,11 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
         return rc;
 
     // Auxiliary words (counted) followed by the statistics record (output).
-    const uint64_t aux_bytes = pl.aux_bytes;  // a multiple of 8
+    // The LDS variant holds its slot array and window in LDS instead, so
+    // only the rest of the counted words are allocated.
+    const bool lds_tab = variant != RP_VARIANT_LINEAR && pl.lds;
+    const uint64_t tab_bytes = ((uint64_t)pl.T * 4 + 7) / 8 * 8 + 2ull * pl.bmw * 4;
+    const uint64_t aux_bytes = lds_tab ? pl.aux_bytes - tab_bytes : pl.aux_bytes;  // multiple of 8
     const uint64_t total = aux_bytes + S_WORDS * 8;
     void *mem = nullptr;
     if (hipMallocAsync(&mem, total, stream) != hipSuccess) {
@@ -945,7 +970,7 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
                     ? (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)))
                     : 1u;
     p.variant = (uint32_t)variant;
-    p.lds_tab = (variant != RP_VARIANT_LINEAR && pl.lds) ? 1u : 0u;
+    p.lds_tab = lds_tab ? 1u : 0u;
     p.hoist = env_int("RP_HOIST", 1) ? 1u : 0u;
     p.bmw = pl.bmw;
     p.dstats = dstats;
@@ -961,10 +986,12 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
             cur += 2ull * pl.G * 8;
         }
     } else if (!pl.single) {
-        p.slots = reinterpret_cast<uint32_t *>(cur);
-        cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
-        p.bm = reinterpret_cast<uint32_t *>(cur);
-        cur += 2ull * pl.bmw * 4;
+        if (!lds_tab) {
+            p.slots = reinterpret_cast<uint32_t *>(cur);
+            cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
+            p.bm = reinterpret_cast<uint32_t *>(cur);
+            cur += 2ull * pl.bmw * 4;
+        }
         if (pl.G > 1) {
             p.flags = reinterpret_cast<uint64_t *>(cur);
             cur += 2ull * pl.G * 8;

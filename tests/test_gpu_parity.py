@@ -167,6 +167,20 @@ def test_schedule_invariance(monkeypatch, grid, slots):
             assert s["grid"] <= int(grid)
 
 
+def test_spare_words_widen_table():
+    """When the grid, not the bound, limits the active swaps, the planner
+    spends spare words on more reservation slots per swap; the output is the
+    same Knuth shuffle."""
+    n, seed = (1 << 24) + 5, 3
+    want = np.arange(n, dtype=np.int64)
+    oracle.knuth_shuffle_seed(want, seed)
+    A = workloads.identity(n, torch.int64, DEV)
+    s = _run(A, seed=seed, eps=0.1)
+    assert s["table_slots"] > s["k"], s
+    assert s["aux_words"] <= s["aux_bound_words"]
+    assert np.array_equal(A.cpu().numpy(), want)
+
+
 def test_repeat_runs_identical():
     n = 300_001
     outs = []
@@ -210,11 +224,18 @@ def test_n2p28(dtype, eps):
     torch.cuda.empty_cache()
 
 
-def test_n2p30_int64():
+@pytest.mark.parametrize("eps", [0.2, 0.5])
+def test_n2p30_int64(eps):
     n, seed = 1 << 30, 1
     A = workloads.identity(n, torch.int64, DEV)
-    s = _run(A, seed=seed, eps=0.5)
-    assert s["aux_bound_words"] == 32768 and s["aux_words"] <= 32768
+    s = _run(A, seed=seed, eps=eps)
+    assert s["aux_bound_words"] == rp.rp_aux_bound_words(n, eps)
+    assert s["aux_words"] <= s["aux_bound_words"]
+    if eps == 0.5:
+        assert s["aux_bound_words"] == 32768
+    else:
+        # the grid caps k; the spare words widen the reservation array
+        assert s["table_slots"] > s["k"]
     assert _is_permutation(A, n)
     _sampled_check(A, n, seed)
     del A
