@@ -53,9 +53,11 @@ extern "C" {
  * Per-call statistics, written by the device and copied into caller memory
  * (host) when the stream reaches the end of the call.
  *   k                 active-swap capacity per round (the prefix size)
- *   aux_words         device memory the call allocated, in 8-byte words
- *                     (rounded up); includes tables, bitmaps, barrier flags
- *                     and counters
+ *   aux_words         auxiliary memory of the call, in 8-byte words
+ *                     (rounded up): the device memory it allocated for
+ *                     tables, bitmaps, barrier flags and counters, plus the
+ *                     LDS that holds the table and window of a
+ *                     one-workgroup launch (which then allocates none)
  *   aux_bound_words   floor(n^(1-eps))
  *   rounds            reserve/commit rounds executed
  *   attempts          swap attempts summed over rounds (self-loops excluded)
