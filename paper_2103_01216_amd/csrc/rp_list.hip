@@ -45,7 +45,7 @@ using namespace rpdev;
 
 constexpr int LWG = 256;
 constexpr int LWAVES = LWG / 64;
-constexpr int LM = 4;                       // block elements per lane
+constexpr int LM_MAX = 4;                   // block elements per lane, at most
 constexpr uint32_t NILI = 0xFFFFFFFFu;
 constexpr uint32_t LMAXG = 2048;
 constexpr uint32_t LPOLL = 8;               // barrier flags a lane loads at once
@@ -191,6 +191,10 @@ __device__ bool grid_sum(const LParams &p, uint32_t *epoch, uint32_t lo, uint32_
     return __builtin_amdgcn_readfirstlane((uint32_t)sh[2]) == 0;
 }
 
+// LM: block elements per lane (1, 2 or 4): the fewest that hold a block on
+// the grid, so that a small block is spread over as many workgroups as it
+// fills.
+template <int LM>
 __global__ __launch_bounds__(LWG) void rp_list_kernel(LParams p)
 {
     __shared__ uint64_t sh[3];
@@ -377,14 +381,25 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return RP_EDEVICE;
-    int occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(rp_list_kernel), LWG, 0) != hipSuccess)
-        return RP_EDEVICE;
-    occ = std::max(occ, 1);
-    // k = floor(n^(1-eps)) elements per block; the grid holds LM per lane.
+    // k = floor(n^(1-eps)) elements per block; the grid holds LM per lane,
+    // the fewest of 1, 2, 4 that hold a whole block (more workgroups with
+    // fewer elements each keep more memory operations in flight per round).
     const uint64_t bound = rp_aux_bound_words(n, eps);
-    const uint64_t gmax = std::min<uint64_t>(LMAXG, (uint64_t)prop.multiProcessorCount * occ);
+    const void *const fns[3] = {reinterpret_cast<const void *>(rp_list_kernel<1>),
+                                reinterpret_cast<const void *>(rp_list_kernel<2>),
+                                reinterpret_cast<const void *>(rp_list_kernel<LM_MAX>)};
+    const uint64_t lms[3] = {1, 2, LM_MAX};
+    int li = 0;
+    uint64_t gmax = 1;
+    for (;; li++) {
+        int occ = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fns[li], LWG, 0) != hipSuccess)
+            return RP_EDEVICE;
+        gmax = std::min<uint64_t>(LMAXG, (uint64_t)prop.multiProcessorCount * std::max(occ, 1));
+        if (li == 2 || bound <= gmax * LWG * lms[li])
+            break;
+    }
+    const uint64_t LM = lms[li];
     // Auxiliary words: flags (two parities) + error word + 3 result words.
     // The grid is limited so that they fit in the bound too.
     uint64_t G = std::min<uint64_t>(gmax, (bound + LWG * LM - 1) / (LWG * LM));
@@ -435,7 +450,7 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
         return RP_EINVAL;
     }
     void *args[] = {&p};
-    if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(rp_list_kernel), dim3((uint32_t)G),
+    if (hipLaunchCooperativeKernel(fns[li], dim3((uint32_t)G),
                                    dim3(LWG), args, 0, stream) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFreeAsync(mem, stream);

@@ -96,6 +96,18 @@ def test_large():
     assert st["phases"] == -(-n // st["k"])
 
 
+@pytest.mark.parametrize("eps", [0.125, 0.05])
+def test_block_elements_per_lane(eps):
+    """Blocks larger than the grid holds at one element per lane (here
+    623K and 1.9M elements) are held with 2 or 4 per lane (which one depends
+    on the kernels' occupancy); the records and ranks are the oracle's
+    either way."""
+    n = 1 << 22
+    prev, nxt = lists(n, 5, 21)
+    st = check(prev, nxt, seed=4, eps=eps)
+    assert -(-st["k"] // (st["grid"] * 256)) in (2, 4), st
+
+
 def test_rejects_inconsistent_links_untouched():
     n = 1000
     prev, nxt = lists(n, 1, 1)
