@@ -107,7 +107,6 @@ struct Params {
     uint32_t T;          // reservation slots
     uint32_t bmw;        // dense-window words per parity
     uint32_t choices;    // reservation slots per key: 1 or 2
-    uint32_t hoist;      // 1: read records before the barrier
     uint32_t *slots;
     uint32_t *bm;
     uint64_t *flags;
@@ -367,22 +366,13 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                 }
             }
         }
-        // Read both records of every active swap now.  If the swap wins this
-        // round, no other winner touches either location, and every earlier
-        // round's writes completed before the gather above, so these values
-        // are exactly the ones the swap exchanges.
-        Rec<EB == 0 ? 4 : EB> r_s[M], r_h[M];
-        if (EB != 0 && p.hoist) {
-#pragma unroll
-            for (int m = 0; m < M; m++)
-                if (src[m] != EMPTY) {
-                    r_s[m].load(p.A, src[m]);
-                    r_h[m].load(p.A, tgt[m]);
-                }
+        // ---- 3. reserve: clean the stale window parity; priority write on
+        // the slot(s) of H[s]; dense window bit
+        {
+            const uint32_t op = par ^ 1u;
+            for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
+                clear_rmw(&bm[(uint64_t)op * p.bmw + i]);
         }
-
-        // ---- 3. reserve: priority write on the two slots of H[s]; dense
-        // window bit; clean the stale window parity
         uint32_t act = 0;
 #pragma unroll
         for (int m = 0; m < M; m++) {
@@ -412,12 +402,27 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        {
-            const uint32_t op = par ^ 1u;
-            for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
-                clear_rmw(&bm[(uint64_t)op * p.bmw + i]);
-        }
         attempts += act;
+
+        // Read both records of every active swap now, after the
+        // reservations.  If the swap wins this round, no other winner touches
+        // either location, and every earlier round's writes completed before
+        // the gather above, so these values are exactly the ones the swap
+        // exchanges.  Exactly two loads per slot are issued (an empty slot
+        // reads record 0 and ignores it), so that the wait below can let
+        // them stay in flight across the barrier: vector memory operations
+        // of a wave complete in issue order, and the barrier needs only the
+        // reservations and the window clears, issued before them.
+        Rec<EB == 0 ? 4 : EB> r_s[M], r_h[M];
+        constexpr bool hoisted = EB != 0;
+        if constexpr (hoisted) {
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                const bool on = src[m] != EMPTY;
+                r_s[m].load(p.A, on ? src[m] : 0u);
+                r_h[m].load(p.A, on ? tgt[m] : 0u);
+            }
+        }
 
         // ---- 4. barrier (wave 0 of workgroup 0 also totals the attempts)
         {
@@ -425,7 +430,10 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             if (lane == 63)
                 sh_wave[wave] = ai;
         }
-        wait_mem();
+        if constexpr (hoisted)
+            wait_mem_but<2 * M * Rec<EB == 0 ? 4 : EB>::LOADS>();
+        else
+            wait_mem();
         __syncthreads();
         ++epoch;
         if (wave == 0) {
@@ -460,10 +468,6 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
                 continue;
             const uint32_t s = src[m], h = tgt[m];
             const uint32_t ds = s - cnew;  // s >= cnew for every active swap
-            if (EB != 0 && !p.hoist) {
-                r_s[m].load(p.A, s);
-                r_h[m].load(p.A, h);
-            }
             if (linear) {
                 // (t2:t1) = R[H[s]], (q2:q1) = R[s]
                 const uint64_t a = ld(&p.R64[h]), b = ld(&p.R64[s]);
@@ -687,12 +691,12 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
         pl->aux_bytes = 8;  // the error word; budget >= 8 since bound >= 1
         return RP_OK;
     }
-    // Largest k that fits with a single workgroup (no flags).
-    auto kmax_for = [&](uint64_t G) {
+    // Largest k that fits on G workgroups with `ratio` slots per swap.
+    auto kmax_for = [&](uint64_t G, double ratio = table_ratio()) {
         uint64_t lo = 0, hi = (uint64_t)n;  // k never needs to exceed n
         while (lo < hi) {
             const uint64_t mid = (lo + hi + 1) / 2;
-            if (aux_bytes_for(mid, G, nullptr, nullptr) <= budget) lo = mid;
+            if (aux_bytes_for(mid, G, nullptr, nullptr, ratio) <= budget) lo = mid;
             else hi = mid - 1;
         }
         return lo;
@@ -730,12 +734,19 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
     // sparser reservation array: with r slots per swap a swap loses to a
     // collision with probability about 1 - r(1 - e^(-1/r)) (37 % at r = 1,
     // 12 % at r = 4), and every such loss costs another round's atomic and
-    // record reads.
+    // record reads.  The largest r is taken for which k need not shrink by
+    // more than a quarter: with k that large the rounds are cheap next to
+    // the attempts, and r = 1.5 at 3/4 of k already completes about as many
+    // swaps per round as r = 1 at the full k.
     double ratio = table_ratio();
     const char *fixed = getenv("RP_TABLE_RATIO");
     if (!(fixed && *fixed) && k < kmax_for(G)) {
         for (const double r : {SPARE_RATIO_MAX, 3.0, 2.0, 1.5, 1.25}) {
-            if (r > ratio && aux_bytes_for(k, G, nullptr, nullptr, r) <= budget) {
+            if (r <= ratio)
+                break;
+            const uint64_t kr = std::min<uint64_t>(k, kmax_for(G, r));
+            if (kr >= 2 && kr * 4 >= k * 3) {
+                k = kr;
                 ratio = r;
                 break;
             }
@@ -971,7 +982,6 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
                     : 1u;
     p.variant = (uint32_t)variant;
     p.lds_tab = lds_tab ? 1u : 0u;
-    p.hoist = env_int("RP_HOIST", 1) ? 1u : 0u;
     p.bmw = pl.bmw;
     p.dstats = dstats;
     p.max_rounds = n + 64;

@@ -43,6 +43,17 @@ __device__ __forceinline__ void wait_mem()
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Wait until at most N of this wave's vector memory operations are still
+// outstanding.  They complete in the order they were issued (the counter the
+// compiler's own waits rely on), so this waits for every operation issued
+// before the last N.
+template <int N>
+__device__ __forceinline__ void wait_mem_but()
+{
+    static_assert(N >= 0 && N < 64, "the vector memory counter has 6 bits");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
 
 // ------------------------------------------------------- exact integer math
 
@@ -127,7 +138,9 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 
 // Records of EB bytes held in registers (EB = 4, 8, 16).
 template <int EB> struct Rec;
+// LOADS: vector memory instructions one load issues.
 template <> struct Rec<4> {
+    static constexpr int LOADS = 1;
     uint32_t w;
     __device__ void load(const unsigned char *A, uint32_t i)
     { w = ld(reinterpret_cast<const uint32_t *>(A) + i); }
@@ -135,6 +148,7 @@ template <> struct Rec<4> {
     { st(reinterpret_cast<uint32_t *>(A) + i, w); }
 };
 template <> struct Rec<8> {
+    static constexpr int LOADS = 1;
     uint64_t w;
     __device__ void load(const unsigned char *A, uint32_t i)
     { w = ld(reinterpret_cast<const uint64_t *>(A) + i); }
@@ -142,6 +156,7 @@ template <> struct Rec<8> {
     { st(reinterpret_cast<uint64_t *>(A) + i, w); }
 };
 template <> struct Rec<16> {
+    static constexpr int LOADS = 2;
     uint64_t w0, w1;
     __device__ void load(const unsigned char *A, uint32_t i)
     {
