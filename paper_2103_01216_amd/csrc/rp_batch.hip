@@ -135,9 +135,19 @@ struct WaveGroup {
     }
 };
 
+// A request's arrays are device global memory.  Its pointers come from the
+// descriptor array, so the compiler cannot see that by itself and would use
+// flat instructions, which also count against the LDS counter: then every
+// LDS wait before a group barrier would also wait for the records in flight.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T *p)
+{
+    return (gptr<T>)p;
+}
+
 __device__ __forceinline__ uint32_t breq_target(const BatchReq &r, uint32_t s)
 {
-    return r.H ? (uint32_t)r.H[s] : seed_target(r.seed, s);
+    return r.H ? (uint32_t)as_global(r.H)[s] : seed_target(r.seed, s);
 }
 
 __device__ __forceinline__ uint32_t lds_ld(const uint32_t *p)
@@ -157,23 +167,23 @@ template <int EB> struct PRec;
 template <> struct PRec<4> {
     uint32_t w;
     __device__ void load(const unsigned char *A, uint32_t i)
-    { w = reinterpret_cast<const uint32_t *>(A)[i]; }
+    { w = as_global(reinterpret_cast<const uint32_t *>(A))[i]; }
     __device__ void store(unsigned char *A, uint32_t i) const
-    { reinterpret_cast<uint32_t *>(A)[i] = w; }
+    { as_global(reinterpret_cast<uint32_t *>(A))[i] = w; }
 };
 template <> struct PRec<8> {
     uint64_t w;
     __device__ void load(const unsigned char *A, uint32_t i)
-    { w = reinterpret_cast<const uint64_t *>(A)[i]; }
+    { w = as_global(reinterpret_cast<const uint64_t *>(A))[i]; }
     __device__ void store(unsigned char *A, uint32_t i) const
-    { reinterpret_cast<uint64_t *>(A)[i] = w; }
+    { as_global(reinterpret_cast<uint64_t *>(A))[i] = w; }
 };
 
 __device__ __forceinline__ void pswap_generic(unsigned char *A, uint32_t eb,
                                               uint32_t a, uint32_t b)
 {
-    uint32_t *pa = reinterpret_cast<uint32_t *>(A + (uint64_t)a * eb);
-    uint32_t *pb = reinterpret_cast<uint32_t *>(A + (uint64_t)b * eb);
+    gptr<uint32_t> pa = as_global(reinterpret_cast<uint32_t *>(A + (uint64_t)a * eb));
+    gptr<uint32_t> pb = as_global(reinterpret_cast<uint32_t *>(A + (uint64_t)b * eb));
     for (uint32_t j = 0; j < eb / 4; j++) {
         const uint32_t x = pa[j], y = pb[j];
         pa[j] = y;
