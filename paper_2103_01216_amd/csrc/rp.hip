@@ -21,15 +21,15 @@
 //               index), as the paper requires;
 //   2. refill   free slots take fresh indices (decreasing), H[s] is computed
 //               (seed mode) or read; self-loops retire at once (Section 4.1
-//               removes them; a swap with H[s] = s is a no-op); both records
-//               of every active swap are read;
+//               removes them; a swap with H[s] = s is a no-op);
 //   3. reserve  the priority write of Algorithm 1 on R[H[s]], into a hashed
 //               reservation array: R[x] is replaced by the slot R'[h1(x)] of
 //               an O(k)-word array (or two slots h1, h2 when two choices are
 //               asked for), updated with an atomic max of the swap's
 //               priority; bit H[s] of the dense window is set when H[s] lies
-//               in it;
-//   4. barrier
+//               in it; then both records of every active swap are read;
+//   4. barrier  (it waits for the reservations only: the record reads stay
+//               in flight across it)
 //   5. commit   swap s wins iff it is still the maximum in a slot of key
 //               H[s] (so no active swap with a larger source, i.e. earlier
 //               in the sequential order, targets H[s]) and no active swap
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
             const uint32_t s = src[m], h = tgt[m];
             const uint32_t ds = s - cnew;
             const uint32_t v = (tag << RANKB) | ds;
-            // Target: still the maximum in one of the two slots of H[s].
+            // Target: still the maximum in a slot of H[s].
             const bool two = p.choices > 1;
             bool win = (t1[m] == v) || (two && t2[m] == v);
             // Source: no active swap targets s.  Such a swap has a larger
