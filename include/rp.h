@@ -165,6 +165,24 @@ int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
                        void *stream, rp_stats *stats);
 
 /*
+ * The auxiliary memory that the calling thread's last rp_shuffle_inplace or
+ * rp_shuffle_variant call obtained, in bytes, as recorded where it was
+ * obtained: the sizes passed to its device allocation calls (the statistics
+ * record excluded) plus the dynamic LDS of its launch.  Lets a caller check
+ * the floor(n^(1-eps))-word bound of Section 3.2 independently of
+ * rp_stats.aux_words.  0 before the first call and after a call that
+ * allocated nothing (n <= 1, or an error before allocating).  Host only;
+ * no device work.
+ *
+ * Two environment variables exercise the error paths of these calls from
+ * the host: RP_FAIL_ALLOC=1 makes the auxiliary allocation fail (the call
+ * returns RP_ENOMEM and A is untouched); RP_MAX_ROUNDS=r lowers the round
+ * limit to r (the call completes with stats->status = RP_ETIMEOUT after r
+ * rounds, and A then holds a permutation of its input, not the shuffle).
+ */
+uint64_t rp_last_call_aux_bytes(void);
+
+/*
  * Seed-mode swap targets on the device, for testing the exact integer path:
  * out[j] = splitmix64(seed ^ idx[j]) mod (idx[j] + 1) for j < count, with
  * idx[j] < 2^32.  idx and out are device arrays.  Stream-ordered.

@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
         L.rp_shuffle_variant.argtypes = [vp, u64, u32, vp, u64, ctypes.c_double, i32, vp, vp]
         L.rp_seed_targets.restype = i32
         L.rp_seed_targets.argtypes = [vp, u64, u64, vp, vp]
+        L.rp_last_call_aux_bytes.restype = u64
+        L.rp_last_call_aux_bytes.argtypes = []
         _lib = L
     return _lib
 
@@ -179,6 +181,12 @@ def _shuffle(A, H, seed, eps, variant, stream, stats):
     if rc != RP_OK:
         raise RpError(rc, "rp_shuffle_inplace" if variant is None else "rp_shuffle_variant")
     return PendingStats(host, stream) if stats else None
+
+
+def rp_last_call_aux_bytes() -> int:
+    """Auxiliary bytes (device allocations plus dynamic LDS) that this
+    thread's last rp_shuffle_inplace / rp_shuffle_variant call obtained."""
+    return int(lib().rp_last_call_aux_bytes())
 
 
 def rp_seed_targets(idx, seed: int, stream=None):

@@ -911,9 +911,32 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
 
 namespace {
 
+// What the calling thread's last shuffle call obtained as auxiliary memory,
+// recorded where it is obtained (allocation calls and the launch's dynamic
+// LDS), independently of the plan's own count.
+struct AuxLedger {
+    uint64_t device_bytes = 0;
+    uint64_t lds_bytes = 0;
+};
+thread_local AuxLedger g_ledger;
+
+// Every counted device allocation of a shuffle call goes through here.
+// RP_FAIL_ALLOC (environment, non-zero) makes it fail, to exercise the
+// RP_ENOMEM path without exhausting the device.
+hipError_t aux_alloc(void **ptr, uint64_t bytes, hipStream_t stream)
+{
+    if (env_int("RP_FAIL_ALLOC", 0) != 0)
+        return hipErrorOutOfMemory;
+    const hipError_t e = hipMallocAsync(ptr, bytes, stream);
+    if (e == hipSuccess)
+        g_ledger.device_bytes += bytes;
+    return e;
+}
+
 int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, uint64_t seed,
                  double eps, int variant, void *stream_, rp_stats *stats)
 {
+    g_ledger = AuxLedger{};
     int rc = validate(A, n, elem_bytes, eps);
     if (rc != RP_OK)
         return rc;
@@ -944,20 +967,28 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     if (rc != RP_OK)
         return rc;
 
-    // Auxiliary words (counted) followed by the statistics record (output).
-    // The LDS variant holds its slot array and window in LDS instead, so
-    // only the rest of the counted words are allocated.
+    // Auxiliary words (counted), and apart from them the statistics record
+    // (output, not counted).  The LDS variant holds its slot array and window
+    // in LDS instead, so only the rest of the counted words are allocated.
     const bool lds_tab = variant != RP_VARIANT_LINEAR && pl.lds;
     const uint64_t tab_bytes = ((uint64_t)pl.T * 4 + 7) / 8 * 8 + 2ull * pl.bmw * 4;
     const uint64_t aux_bytes = lds_tab ? pl.aux_bytes - tab_bytes : pl.aux_bytes;  // multiple of 8
-    const uint64_t total = aux_bytes + S_WORDS * 8;
-    void *mem = nullptr;
-    if (hipMallocAsync(&mem, total, stream) != hipSuccess) {
+    void *mem = nullptr, *smem = nullptr;
+    if (aux_alloc(&mem, aux_bytes, stream) != hipSuccess) {
         (void)hipGetLastError();
         return RP_ENOMEM;
     }
+    if (hipMallocAsync(&smem, S_WORDS * 8, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFreeAsync(mem, stream);
+        return RP_ENOMEM;
+    }
+    auto release = [&]() {
+        (void)hipFreeAsync(smem, stream);
+        return hipFreeAsync(mem, stream);
+    };
     unsigned char *base = static_cast<unsigned char *>(mem);
-    uint64_t *dstats = reinterpret_cast<uint64_t *>(base + aux_bytes);
+    uint64_t *dstats = static_cast<uint64_t *>(smem);
     rp_stats hs;
     fill_host_stats(pl, &hs);
     const uint32_t init_blocks =
@@ -965,7 +996,7 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     rp_init_kernel<<<init_blocks, 256, 0, stream>>>(reinterpret_cast<uint32_t *>(base),
                                                     aux_bytes / 4, dstats, hs);
     if (hipGetLastError() != hipSuccess) {
-        (void)hipFreeAsync(mem, stream);
+        (void)release();
         return RP_EDEVICE;
     }
 
@@ -984,7 +1015,11 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     p.lds_tab = lds_tab ? 1u : 0u;
     p.bmw = pl.bmw;
     p.dstats = dstats;
-    p.max_rounds = n + 64;
+    // RP_MAX_ROUNDS (environment) lowers the round limit, to exercise the
+    // watchdog path: every workgroup leaves at that round and the call
+    // reports RP_ETIMEOUT with A holding a permutation of its input.
+    const int max_rounds = env_int("RP_MAX_ROUNDS", 0);
+    p.max_rounds = max_rounds > 0 ? (uint64_t)max_rounds : n + 64;
     // Carve the counted words: [slots | bm | flags | err], or for the linear
     // variant [R (n words) | flags | err].
     unsigned char *cur = base;
@@ -1017,11 +1052,11 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(&herr, p.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess) {
-            (void)hipFreeAsync(mem, stream);
+            (void)release();
             return RP_EDEVICE;
         }
         if (herr != 0) {
-            (void)hipFreeAsync(mem, stream);
+            (void)release();
             return RP_EINVAL;
         }
     }
@@ -1029,28 +1064,29 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     if (pl.single) {
         rp_single_kernel<<<1, 64, 0, stream>>>(p);
         if (hipGetLastError() != hipSuccess) {
-            (void)hipFreeAsync(mem, stream);
+            (void)release();
             return RP_EDEVICE;
         }
     } else {
         KernelFn fn = p.lds_tab ? pick_lds_kernel(pl.eb_class) : pick_kernel((int)pl.M, pl.eb_class);
         void *args[] = {&p};
         const size_t lds_bytes = p.lds_tab ? ((size_t)pl.T + 2 * (size_t)pl.bmw) * 4 : 0;
+        g_ledger.lds_bytes = lds_bytes;
         if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(pl.G),
                                        dim3(WG), args, lds_bytes, stream) != hipSuccess) {
             (void)hipGetLastError();
-            (void)hipFreeAsync(mem, stream);
+            (void)release();
             return RP_EDEVICE;
         }
     }
     if (stats) {
         if (hipMemcpyAsync(stats, dstats, sizeof(rp_stats), hipMemcpyDeviceToHost,
                            stream) != hipSuccess) {
-            (void)hipFreeAsync(mem, stream);
+            (void)release();
             return RP_EDEVICE;
         }
     }
-    if (hipFreeAsync(mem, stream) != hipSuccess)
+    if (release() != hipSuccess)
         return RP_EDEVICE;
     return RP_OK;
 }
@@ -1071,6 +1107,11 @@ int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
                        void *stream, rp_stats *stats)
 {
     return shuffle_impl(A, n, elem_bytes, H, seed, eps, variant, stream, stats);
+}
+
+uint64_t rp_last_call_aux_bytes(void)
+{
+    return g_ledger.device_bytes + g_ledger.lds_bytes;
 }
 
 int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,

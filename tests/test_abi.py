@@ -102,6 +102,14 @@ def test_trivial_sizes_are_noops_without_device():
     assert L.rp_shuffle_inplace(None, 0, 8, None, 0, 0.5, None, ctypes.byref(s)) == rp.RP_OK
     assert L.rp_shuffle_inplace(ctypes.c_void_p(16), 1, 8, None, 0, 0.5, None, ctypes.byref(s)) == rp.RP_OK
     assert s.rounds == 0
+    # nothing was allocated by either call
+    assert rp.rp_last_call_aux_bytes() == 0
+
+
+def test_rejected_call_allocates_nothing():
+    L = rp.lib()
+    assert L.rp_shuffle_inplace(None, 5, 8, None, 0, 0.5, None, None) == rp.RP_EINVAL
+    assert rp.rp_last_call_aux_bytes() == 0
 
 
 def test_workload_splitmix_matches_oracle():
