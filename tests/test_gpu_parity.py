@@ -242,6 +242,29 @@ def test_n2p30_int64(eps):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("eps", [0.25, 0.5])
+def test_h_mode_n2p26(eps):
+    """Explicit targets at a size that spans the whole grid: exactly uniform
+    H[i] in [0, i] from a seeded host generator, read by the kernel instead of
+    computed; permutation + sampled positions against the oracle's sampled
+    form over the same H."""
+    n = 1 << 26
+    rng = np.random.default_rng(2026)
+    H = rng.integers(0, np.arange(1, n + 1, dtype=np.int64), dtype=np.int64)
+    A = workloads.identity(n, torch.int64, DEV)
+    s = _run(A, H=torch.from_numpy(H).to(DEV), eps=eps)
+    assert s["aux_words"] <= s["aux_bound_words"] == rp.rp_aux_bound_words(n, eps)
+    assert s["self_loops"] == int(np.sum(H == np.arange(n)))
+    assert _is_permutation(A, n)
+    pos = np.unique(np.concatenate([[0, 1, n - 2, n - 1],
+                                    np.random.default_rng(7).integers(0, n, 1024)]))
+    src = oracle.sample_sources(n, pos, H=H.astype(np.uint64))
+    got = A[torch.from_numpy(pos.astype(np.int64)).to(DEV)].cpu().numpy()
+    assert np.array_equal(got.astype(np.int64), src.astype(np.int64))
+    del A
+    torch.cuda.empty_cache()
+
+
 def test_records64_n2p26():
     n, seed = 1 << 26, 1
     A = workloads.records64(n, DEV)
