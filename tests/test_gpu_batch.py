@@ -72,7 +72,7 @@ def test_batch_eps(eps):
         assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(n), seeds[i]))
 
 
-@pytest.mark.parametrize("eb", [8, 16, 64])
+@pytest.mark.parametrize("eb", [8, 12, 16, 64, 256])
 def test_batch_record_sizes(eb):
     sizes = workloads.batch_sizes(24, 3, 14, 5)
     seeds = list(range(len(sizes)))

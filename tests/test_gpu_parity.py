@@ -66,7 +66,7 @@ def test_seed_targets_exact_mod():
 
 @pytest.mark.parametrize("n", [2, 3, 7, 8, 1000, (1 << 16) + 3])
 @pytest.mark.parametrize("eps", [0.1, 0.5, 0.9])
-@pytest.mark.parametrize("eb", [4, 8, 16, 64, 12])
+@pytest.mark.parametrize("eb", [4, 8, 16, 64, 12, 252, 256])
 def test_seed_mode_parity_small(n, eps, eb):
     for seed in (0, 1):
         host = _host_records(n, eb, seed + 17)
