@@ -106,12 +106,13 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
 /*
  * Shuffle A in place (Section 4.1; the RP-Final implementation of
  * Section 7.4 / Appendix A.2).
- *   A           n records of elem_bytes bytes each, contiguous (device).
- *               Permuted in place; the caller owns it.
+ *   A           n records of elem_bytes bytes each, contiguous (device),
+ *               aligned to 8 bytes when elem_bytes is a multiple of 8 and to
+ *               4 otherwise.  Permuted in place; the caller owns it.
  *   n           number of records, n < 2^32.  n <= 1 is a successful no-op.
  *   elem_bytes  record size: a multiple of 4 in [4, 256].
  *   H           swap targets, n uint64 values with H[i] <= i (device,
- *               read-only, not counted as auxiliary space), or NULL for
+ *               8-byte aligned, read-only, not counted as auxiliary space), or NULL for
  *               seed mode: H[i] = splitmix64(seed ^ i) mod (i + 1), with
  *               SplitMix64 as published by Steele, Lea and Flood (2014).
  *   seed        used only in seed mode.
@@ -122,7 +123,8 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
  *               synchronous copy) receiving rp_stats when the stream reaches
  *               the end of the call; may be NULL.
  * Errors: RP_EINVAL for A == NULL with n > 1, a bad elem_bytes or eps,
- * n >= 2^32, or (H mode) some H[i] > i -- H mode validates H on the device
+ * n >= 2^32, a misaligned A or H (checked on the host, before any device
+ * work), or (H mode) some H[i] > i -- H mode validates H on the device
  * first and, for that check only, waits for the stream before returning.
  * RP_ENOMEM if device memory for the auxiliary structures cannot be had.
  * RP_EDEVICE if a HIP call fails.  A is untouched whenever an error is
@@ -200,11 +202,13 @@ int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
  * stream-ordered; completion can be observed without blocking.
  */
 typedef struct rp_batch_request {
-    void *A;                 /* device records, permuted in place (caller-owned) */
+    void *A;                 /* device records, permuted in place (caller-owned);
+                                aligned as for rp_shuffle_inplace */
     uint64_t n;              /* number of records, < 2^32 */
     uint32_t elem_bytes;     /* multiple of 4 in [4, 256]; equal for the batch */
     uint32_t reserved;       /* 0 */
-    const uint64_t *H;       /* device targets (H[i] <= i) or NULL: seed mode */
+    const uint64_t *H;       /* device targets (H[i] <= i, 8-byte aligned) or NULL:
+                                seed mode */
     uint64_t seed;           /* seed mode: H[i] = splitmix64(seed ^ i) mod (i+1) */
     double eps;              /* in (0, 1) */
 } rp_batch_request;
@@ -277,7 +281,8 @@ int rp_batch_release(uint64_t batch_id);
  * has the Decomposable Property, so Algorithm 2 can be applied to
  * n^(1-eps) elements at a time).
  *
- * rec: device array of 2n words, element i's (prev, next) pair.  On input
+ * rec: device array of 2n words, element i's (prev, next) pair (rec, rank
+ * and prio are 8-byte aligned; RP_EINVAL otherwise).  On input
  * the low 32 bits of rec[2i] and rec[2i+1] are the previous and next
  * element (0xFFFFFFFF = none; any number of disjoint lists; the high bits
  * are ignored).  The elements are contracted in blocks of

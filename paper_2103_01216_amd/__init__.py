@@ -541,6 +541,17 @@ class rp_list_stats(ctypes.Structure):
                  "rebuild_rounds", "grid")] + [("status", ctypes.c_int64)]
 
 
+def _list_lib():
+    L = lib()
+    if not getattr(L, "_list_ready", False):
+        vp = ctypes.c_void_p
+        L.rp_list_rank.restype = ctypes.c_int
+        L.rp_list_rank.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64, ctypes.c_double,
+                                   vp, vp, ctypes.POINTER(rp_list_stats)]
+        L._list_ready = True
+    return L
+
+
 def rp_list_rank(rec, *, prio=None, seed: int = 0, eps: float = 0.5, rank=None,
                  stream=None, stats: bool = True):
     """List ranking by in-place list contraction (rp_list_rank of include/rp.h).
@@ -550,13 +561,7 @@ def rp_list_rank(rec, *, prio=None, seed: int = 0, eps: float = 0.5, rank=None,
     Returns (rank tensor, stats dict or None).
     """
     import torch
-    L = lib()
-    if not getattr(L, "_list_ready", False):
-        vp = ctypes.c_void_p
-        L.rp_list_rank.restype = ctypes.c_int
-        L.rp_list_rank.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64, ctypes.c_double,
-                                   vp, vp, ctypes.POINTER(rp_list_stats)]
-        L._list_ready = True
+    L = _list_lib()
     if not rec.is_cuda or not rec.is_contiguous() or rec.element_size() != 8 or \
             rec.dim() != 2 or rec.shape[1] != 2:
         raise ValueError("rec must be a contiguous (n, 2) 64-bit device tensor")

@@ -773,6 +773,8 @@ int validate(void *A, uint64_t n, uint32_t eb, double eps)
         return RP_EINVAL;
     if (A == nullptr && n > 1)
         return RP_EINVAL;
+    if (n > 1 && (reinterpret_cast<uintptr_t>(A) & (record_alignment(eb) - 1u)) != 0)
+        return RP_EINVAL;
     return RP_OK;
 }
 
@@ -880,7 +882,8 @@ uint64_t rp_aux_bound_words(uint64_t n, double eps)
 int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
             rp_stats *stats_out)
 {
-    int rc = validate((void *)1, n, elem_bytes, eps);
+    // Sizing only: any non-null, suitably aligned stand-in for A.
+    int rc = validate(reinterpret_cast<void *>(uintptr_t{256}), n, elem_bytes, eps);
     if (rc != RP_OK)
         return rc;
     int occ[4];
@@ -941,6 +944,8 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     if (rc != RP_OK)
         return rc;
     if (variant < RP_VARIANT_FINAL || variant > RP_VARIANT_LINEAR)
+        return RP_EINVAL;
+    if (H != nullptr && (reinterpret_cast<uintptr_t>(H) & 7u) != 0)
         return RP_EINVAL;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     if (n <= 1) {

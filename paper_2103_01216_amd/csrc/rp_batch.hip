@@ -613,6 +613,10 @@ bool valid_request(const rp_batch_request &q)
         return false;
     if (q.A == nullptr && q.n > 1)
         return false;
+    if (q.n > 1 && (reinterpret_cast<uintptr_t>(q.A) & (record_alignment(q.elem_bytes) - 1u)) != 0)
+        return false;
+    if (q.H != nullptr && (reinterpret_cast<uintptr_t>(q.H) & 7u) != 0)
+        return false;
     return true;
 }
 

@@ -38,6 +38,13 @@ __device__ __forceinline__ void clear_rmw(uint32_t *p)
     (void)__hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Alignment a record array needs: records whose size is a multiple of 8
+// bytes are moved in 8-byte words, the others in 4-byte words.
+__host__ __device__ inline uint32_t record_alignment(uint32_t eb)
+{
+    return (eb & 7u) == 0 ? 8u : 4u;
+}
+
 __device__ __forceinline__ void wait_mem()
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");

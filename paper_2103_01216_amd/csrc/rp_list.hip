@@ -372,6 +372,9 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
         return RP_EINVAL;
     if (n > 0 && (rec == nullptr || rank == nullptr))
         return RP_EINVAL;
+    if (((reinterpret_cast<uintptr_t>(rec) | reinterpret_cast<uintptr_t>(rank) |
+          reinterpret_cast<uintptr_t>(prio)) & 7u) != 0)
+        return RP_EINVAL;   // 64-bit words
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     if (stats)
         std::memset(stats, 0, sizeof(*stats));

@@ -106,6 +106,28 @@ def test_trivial_sizes_are_noops_without_device():
     assert rp.rp_last_call_aux_bytes() == 0
 
 
+def test_rejects_misaligned_arrays():
+    """Records move in 8-byte words when their size is a multiple of 8 and in
+    4-byte words otherwise; targets, list words and ranks are 64-bit.  A
+    misaligned array is refused before any device work."""
+    L = rp.lib()
+    assert L.rp_shuffle_inplace(ctypes.c_void_p(4), 5, 8, None, 0, 0.5, None, None) == rp.RP_EINVAL
+    assert L.rp_shuffle_inplace(ctypes.c_void_p(2), 5, 12, None, 0, 0.5, None, None) == rp.RP_EINVAL
+    assert L.rp_shuffle_inplace(ctypes.c_void_p(12), 5, 64, None, 0, 0.5, None, None) == rp.RP_EINVAL
+    assert L.rp_shuffle_inplace(ctypes.c_void_p(16), 5, 8, ctypes.c_void_p(4), 0, 0.5, None,
+                                None) == rp.RP_EINVAL
+    assert L.rp_shuffle_variant(ctypes.c_void_p(4), 5, 8, None, 0, 0.5, 0, None, None) == rp.RP_EINVAL
+    rec = rp._list_lib().rp_list_rank
+    assert rec(ctypes.c_void_p(4), 5, None, 0, 0.5, ctypes.c_void_p(16), None, None) == rp.RP_EINVAL
+    assert rec(ctypes.c_void_p(16), 5, None, 0, 0.5, ctypes.c_void_p(20), None, None) == rp.RP_EINVAL
+    assert rec(ctypes.c_void_p(16), 5, ctypes.c_void_p(3), 0, 0.5, ctypes.c_void_p(16), None,
+               None) == rp.RP_EINVAL
+    bad = rp.rp_batch_request(ctypes.c_void_p(4), 5, 8, 0, None, 1, 0.5)
+    bid = ctypes.c_uint64(0)
+    assert rp._batch_lib().rp_batch_submit(ctypes.byref(bad), 1, None, None,
+                                           ctypes.byref(bid)) == rp.RP_EINVAL
+
+
 def test_rejected_call_allocates_nothing():
     L = rp.lib()
     assert L.rp_shuffle_inplace(None, 5, 8, None, 0, 0.5, None, None) == rp.RP_EINVAL
