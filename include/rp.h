@@ -367,7 +367,9 @@ typedef struct rp_server_config {
                                     works on it) instead of in one workgroup
                                     of a batched launch; when more than 4
                                     wait, batch them */
-    rp_batch_schedule schedule;  /* all zero: the tuned or default schedule */
+    rp_batch_schedule schedule;  /* small requests' schedule; all zero: 1024-lane
+                                    workgroups, two per compute unit, the
+                                    shortest launches (lowest latency) */
 } rp_server_config;
 
 typedef struct rp_server_request {

@@ -521,7 +521,17 @@ int launch_batched(Server &s, int cls)
         large.table_ratio_x16 = have_sched && sc.table_ratio_x16 ? sc.table_ratio_x16 : 24;
         large.workgroups_per_cu = 2;
         large.workgroup_lanes = 1024;
-        const rp_batch_schedule *use = cls == 1 ? &large : (have_sched ? &sc : nullptr);
+        // Small requests without a configured schedule: 1024-lane
+        // workgroups, two per compute unit.  A launch lasts as long as its
+        // largest request, and requests arriving meanwhile wait for a free
+        // stream, so the shortest launches (the most lanes per request) give
+        // the lowest latency under load.
+        rp_batch_schedule small{};
+        small.wave_cutoff = 1u << 14;
+        small.table_ratio_x16 = 16;
+        small.workgroups_per_cu = 2;
+        small.workgroup_lanes = 1024;
+        const rp_batch_schedule *use = cls == 1 ? &large : (have_sched ? &sc : &small);
         rc = rp_batch_submit(br.data(), (uint32_t)br.size(), use, s.streams[si], &L.batch_id);
     }
     if (rc != RP_OK) {
@@ -638,13 +648,39 @@ void dispatcher(Server *sp)
     }
 }
 
+// The servers' streams, created once per device and process and shared by
+// every server on that device: the runtime spreads a process's streams over
+// a few hardware queues in creation order, so a fresh set per server could
+// leave a small-request stream on the same hardware queue as a large-request
+// one (small launches then wait behind large ones), depending on how many
+// streams the process created before.
+std::mutex g_stream_mu;
+std::map<int, std::vector<hipStream_t>> g_streams;
+
+int server_streams(int device, hipStream_t *out)
+{
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    auto it = g_streams.find(device);
+    if (it == g_streams.end()) {
+        std::vector<hipStream_t> v(N_STREAMS, nullptr);
+        for (int i = 0; i < N_STREAMS; i++)
+            if (hipStreamCreateWithFlags(&v[i], hipStreamNonBlocking) != hipSuccess) {
+                for (int j = 0; j < i; j++)
+                    (void)hipStreamDestroy(v[j]);
+                return RP_EDEVICE;
+            }
+        it = g_streams.emplace(device, std::move(v)).first;
+    }
+    for (int i = 0; i < N_STREAMS; i++)
+        out[i] = it->second[i];
+    return RP_OK;
+}
+
 void destroy_server(Server *s)
 {
     for (int i = 0; i < N_STREAMS; i++) {
-        if (s->streams[i]) {
-            (void)hipStreamSynchronize(s->streams[i]);
-            (void)hipStreamDestroy(s->streams[i]);
-        }
+        if (s->streams[i])
+            (void)hipStreamSynchronize(s->streams[i]);   // shared: not destroyed
         if (s->bufs[i].host)
             (void)hipHostFree(s->bufs[i].host);
         if (s->bufs[i].dev)
@@ -692,11 +728,10 @@ int rp_server_create(const rp_server_config *cfg, uint64_t *server)
         return RP_ENOMEM;
     }
     s->arena.reset(s->cfg.mem_budget_bytes / rpserve::ALIGN * rpserve::ALIGN);
-    for (int i = 0; i < N_STREAMS; i++)
-        if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
-            destroy_server(s);
-            return RP_EDEVICE;
-        }
+    if (server_streams(s->device, s->streams) != RP_OK) {
+        destroy_server(s);
+        return RP_EDEVICE;
+    }
     s->thread = std::thread(dispatcher, s);
     std::lock_guard<std::mutex> lk(g_smu);
     *server = g_next_server++;
