@@ -276,6 +276,33 @@ int rp_batch_results(uint64_t batch_id, rp_batch_result *out);
 /* Waits for the batch and frees its bookkeeping; the id becomes invalid. */
 int rp_batch_release(uint64_t batch_id);
 
+/*
+ * Several independent shuffles in one cooperative launch, each on all the
+ * workgroups it would get alone: for running a few large shuffles side by
+ * side (one cooperative launch at a time is what the device runs).  Each
+ * request is the operation of rp_shuffle_inplace on its own array, planned
+ * exactly as a call of its own would be (the same k and auxiliary words,
+ * floor(n^(1-eps)) per request, allocated apart for each), on its own group
+ * of workgroups whose rounds are synchronised among themselves only; the
+ * result of each is its Knuth shuffle, whatever else runs in the group.  A
+ * request whose bound holds no table (k = 1) runs as the sequential loop
+ * ahead of the group, as it would alone.
+ *   reqs    host array of count requests (fields as for rp_batch_submit),
+ *           count <= 8, one elem_bytes for all.
+ *   stream  hipStream_t (as void*), or NULL.  Stream-ordered.
+ *   stats   host array of count rp_stats, filled when the stream reaches the
+ *           end of the call, or NULL.
+ * Errors: RP_EINVAL for a request rp_shuffle_inplace would reject, mixed
+ * record sizes, count > 8, a request whose plan needs more than one swap
+ * slot per lane (it fills the device by itself), groups that together do not
+ * fit one launch on the device, or (explicit targets) some H[i] > i in any
+ * request (checked first; the call then waits for the stream).  RP_ENOMEM,
+ * RP_EDEVICE.  Every A is untouched whenever an error is returned.
+ * rp_last_call_aux_bytes reports the sum over the group.
+ */
+int rp_shuffle_group(const rp_batch_request *reqs, uint32_t count, void *stream,
+                     rp_stats *stats);
+
 /* ------------------------------------------------------------------------
  * List ranking by in-place list contraction (Section 4.2: list contraction
  * has the Decomposable Property, so Algorithm 2 can be applied to

@@ -317,6 +317,28 @@ class Batch:
                 raise RpError(rc, "rp_batch_release")
 
 
+def rp_shuffle_group(arrays, *, seeds=None, H=None, eps: float = 0.5, stream=None):
+    """Up to 8 independent shuffles in one cooperative launch (rp_shuffle_group
+    of include/rp.h), each planned as rp_shuffle_inplace would plan it alone.
+    Waits for the stream and returns one statistics dict per array."""
+    import torch
+    L = _batch_lib()
+    if not getattr(L, "_group_ready", False):
+        L.rp_shuffle_group.restype = ctypes.c_int
+        L.rp_shuffle_group.argtypes = [ctypes.POINTER(rp_batch_request), ctypes.c_uint32,
+                                       ctypes.c_void_p, ctypes.POINTER(rp_stats)]
+        L._group_ready = True
+    reqs = _requests(arrays, seeds, H, eps)
+    if stream is None:
+        stream = torch.cuda.current_stream(arrays[0].device) if arrays else torch.cuda.current_stream()
+    st = (rp_stats * max(1, len(arrays)))()
+    rc = L.rp_shuffle_group(reqs, len(arrays), ctypes.c_void_p(stream.cuda_stream), st)
+    if rc != RP_OK:
+        raise RpError(rc, "rp_shuffle_group")
+    stream.synchronize()
+    return [_stats_dict(st[i]) for i in range(len(arrays))]
+
+
 def rp_batch_requests(arrays, *, seeds=None, H=None, eps: float = 0.5):
     """Marshal the request descriptors once, for repeated submits of the same
     arrays (pass the result as `requests=` to rp_batch_submit)."""

@@ -116,6 +116,8 @@ struct Params {
     uint32_t variant;    // RP_VARIANT_*: how reservations are held and checked
     uint32_t lds_tab;    // 1: the launch uses the LDS variant of the kernel
     uint64_t *R64;       // RP_VARIANT_LINEAR: one priority word per position
+    uint32_t wg_first;   // this shuffle's workgroups: [wg_first, wg_first + wg_count)
+    uint32_t wg_count;   // of the launch (all of it, except in a group launch)
 };
 
 // rp_stats word indices
@@ -141,11 +143,11 @@ template <typename Visit>
 __device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t epoch,
                                              uint64_t payload, Visit visit)
 {
-    const uint32_t G = gridDim.x, lane = threadIdx.x & 63;
+    const uint32_t G = p.wg_count, lane = threadIdx.x & 63;
     const uint32_t e16 = epoch & 0xFFFFu;
     uint64_t *fl = p.flags + (uint64_t)(epoch & 1u) * G;
     if (lane == 0)
-        st(&fl[blockIdx.x], ((uint64_t)e16 << 48) | payload);
+        st(&fl[blockIdx.x - p.wg_first], ((uint64_t)e16 << 48) | payload);
     // Poll every flag this lane covers at once; look at the clock and the
     // error word only every 64 sweeps so that a sweep costs one load latency.
     const int nj = (int)((G + 63u) / 64u);
@@ -200,7 +202,7 @@ __device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t epoch,
     __syncthreads();
     if ((threadIdx.x >> 6) == 0) {
         bool ok = true;
-        if (gridDim.x > 1)
+        if (p.wg_count > 1)
             ok = gather_wave0(p, epoch, 0, [](uint32_t, uint64_t) {});
         if ((threadIdx.x & 63) == 0)
             sh_res[3] = ok ? 0u : 1u;
@@ -209,17 +211,18 @@ __device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t epoch,
     return sh_res[3] == 0;
 }
 
-// M: swap slots per lane.  EB: record size held in registers (4, 8, 16), or
-// 0 for any multiple of 4 up to 256 bytes, moved after the decision.  LDS: a
-// one-workgroup launch whose slot array and window live in dynamic LDS.
+// The rounds of one shuffle on its workgroups.  M: swap slots per lane.  EB:
+// record size held in registers (4, 8, 16), or 0 for any multiple of 4 up to
+// 256 bytes, moved after the decision.  LDS: a one-workgroup launch whose
+// slot array and window live in dynamic LDS.
 template <int M, int EB, bool LDS>
-__global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
+__device__ __forceinline__ void rounds_body(const Params &p)
 {
     __shared__ uint32_t sh_wave[WAVES];
     __shared__ uint32_t sh_age[WAVES];
     __shared__ uint64_t sh_res[5];
 
-    const uint32_t G = gridDim.x, w = blockIdx.x, t = threadIdx.x;
+    const uint32_t G = p.wg_count, w = blockIdx.x - p.wg_first, t = threadIdx.x;
     const uint32_t wave = t >> 6, lane = t & 63;
     // Dense window only in the final variant: the one-reservation variant
     // checks sources through the hashed slots, the two-reservation one
@@ -547,6 +550,31 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
     }
 }
 
+template <int M, int EB, bool LDS>
+__global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
+{
+    rounds_body<M, EB, LDS>(p);
+}
+
+// Several independent shuffles in one cooperative launch: shuffle i runs on
+// workgroups [g[i].wg_first, g[i].wg_first + g[i].wg_count) with its own
+// auxiliary words, its rounds synchronised among those workgroups only.
+constexpr uint32_t GROUP_MAX = 8;
+struct GroupParams {
+    uint32_t count;
+    uint32_t pad;
+    Params g[GROUP_MAX];
+};
+
+template <int M, int EB>
+__global__ __launch_bounds__(WG) void rp_rounds_group_kernel(GroupParams gp)
+{
+    uint32_t i = 0;
+    while (i + 1 < gp.count && blockIdx.x >= gp.g[i].wg_first + gp.g[i].wg_count)
+        i++;
+    rounds_body<M, EB, false>(gp.g[i]);
+}
+
 // k = 1: a single active swap per round always commits, so the rounds are the
 // sequential loop itself; used when the auxiliary bound cannot hold a table.
 __global__ void rp_single_kernel(Params p)
@@ -802,6 +830,20 @@ KernelFn pick_lds_kernel(int ebc)
     }
 }
 
+using GroupFn = void (*)(GroupParams);
+
+// Group launches: one slot per lane (a shuffle that needs more fills the
+// device by itself and has nothing to share a launch with).
+GroupFn pick_group_kernel(int ebc)
+{
+    switch (ebc) {
+    case 4: return rp_rounds_group_kernel<1, 4>;
+    case 8: return rp_rounds_group_kernel<1, 8>;
+    case 16: return rp_rounds_group_kernel<1, 16>;
+    default: return rp_rounds_group_kernel<1, 0>;
+    }
+}
+
 KernelFn pick_kernel(int M, int ebc)
 {
     switch (M) {
@@ -914,6 +956,58 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
 
 namespace {
 
+// The launch parameters of one shuffle planned as `pl`, with its counted
+// words at `base` and its statistics record at `dstats`.  The counted words
+// are carved as [slots | bm | flags | err], or for the linear variant
+// [R (n words) | flags | err]; the LDS variant holds slots and window in LDS.
+void setup_params(Params &p, const Plan &pl, int variant, bool lds_tab, void *A, uint64_t n,
+                  uint32_t elem_bytes, const uint64_t *H, uint64_t seed, unsigned char *base,
+                  uint64_t *dstats)
+{
+    p.A = static_cast<unsigned char *>(A);
+    p.H = H;
+    p.seed = seed;
+    p.n = (uint32_t)n;
+    p.eb = elem_bytes;
+    p.k = pl.k;
+    p.T = pl.T;
+    p.choices = variant == RP_VARIANT_FINAL
+                    ? (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)))
+                    : 1u;
+    p.variant = (uint32_t)variant;
+    p.lds_tab = lds_tab ? 1u : 0u;
+    p.bmw = pl.bmw;
+    p.dstats = dstats;
+    // RP_MAX_ROUNDS (environment) lowers the round limit, to exercise the
+    // watchdog path: every workgroup leaves at that round and the call
+    // reports RP_ETIMEOUT with A holding a permutation of its input.
+    const int max_rounds = env_int("RP_MAX_ROUNDS", 0);
+    p.max_rounds = max_rounds > 0 ? (uint64_t)max_rounds : n + 64;
+    p.wg_first = 0;
+    p.wg_count = pl.G;
+    unsigned char *cur = base;
+    if (variant == RP_VARIANT_LINEAR) {
+        p.R64 = reinterpret_cast<uint64_t *>(cur);
+        cur += n * 8;
+        if (pl.G > 1) {
+            p.flags = reinterpret_cast<uint64_t *>(cur);
+            cur += 2ull * pl.G * 8;
+        }
+    } else if (!pl.single) {
+        if (!lds_tab) {
+            p.slots = reinterpret_cast<uint32_t *>(cur);
+            cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
+            p.bm = reinterpret_cast<uint32_t *>(cur);
+            cur += 2ull * pl.bmw * 4;
+        }
+        if (pl.G > 1) {
+            p.flags = reinterpret_cast<uint64_t *>(cur);
+            cur += 2ull * pl.G * 8;
+        }
+    }
+    p.err = reinterpret_cast<uint32_t *>(cur);
+}
+
 // What the calling thread's last shuffle call obtained as auxiliary memory,
 // recorded where it is obtained (allocation calls and the launch's dynamic
 // LDS), independently of the plan's own count.
@@ -1006,49 +1100,7 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     }
 
     Params p{};
-    p.A = static_cast<unsigned char *>(A);
-    p.H = H;
-    p.seed = seed;
-    p.n = (uint32_t)n;
-    p.eb = elem_bytes;
-    p.k = pl.k;
-    p.T = pl.T;
-    p.choices = variant == RP_VARIANT_FINAL
-                    ? (uint32_t)std::max(1, std::min(2, env_int("RP_CHOICES", 1)))
-                    : 1u;
-    p.variant = (uint32_t)variant;
-    p.lds_tab = lds_tab ? 1u : 0u;
-    p.bmw = pl.bmw;
-    p.dstats = dstats;
-    // RP_MAX_ROUNDS (environment) lowers the round limit, to exercise the
-    // watchdog path: every workgroup leaves at that round and the call
-    // reports RP_ETIMEOUT with A holding a permutation of its input.
-    const int max_rounds = env_int("RP_MAX_ROUNDS", 0);
-    p.max_rounds = max_rounds > 0 ? (uint64_t)max_rounds : n + 64;
-    // Carve the counted words: [slots | bm | flags | err], or for the linear
-    // variant [R (n words) | flags | err].
-    unsigned char *cur = base;
-    if (variant == RP_VARIANT_LINEAR) {
-        p.R64 = reinterpret_cast<uint64_t *>(cur);
-        cur += n * 8;
-        if (pl.G > 1) {
-            p.flags = reinterpret_cast<uint64_t *>(cur);
-            cur += 2ull * pl.G * 8;
-        }
-    } else if (!pl.single) {
-        if (!lds_tab) {
-            p.slots = reinterpret_cast<uint32_t *>(cur);
-            cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
-            p.bm = reinterpret_cast<uint32_t *>(cur);
-            cur += 2ull * pl.bmw * 4;
-        }
-        if (pl.G > 1) {
-            p.flags = reinterpret_cast<uint64_t *>(cur);
-            cur += 2ull * pl.G * 8;
-        }
-    }
-    p.err = reinterpret_cast<uint32_t *>(cur);
-    cur += 8;
+    setup_params(p, pl, variant, lds_tab, A, n, elem_bytes, H, seed, base, dstats);
 
     if (H != nullptr) {
         // H mode: reject H[i] > i before anything moves.
@@ -1117,6 +1169,179 @@ int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
 uint64_t rp_last_call_aux_bytes(void)
 {
     return g_ledger.device_bytes + g_ledger.lds_bytes;
+}
+
+int rp_shuffle_group(const rp_batch_request *reqs, uint32_t count, void *stream_,
+                     rp_stats *stats)
+{
+    g_ledger = AuxLedger{};
+    if (count == 0)
+        return RP_OK;
+    if (reqs == nullptr || count > GROUP_MAX)
+        return RP_EINVAL;
+    const uint32_t eb = reqs[0].elem_bytes;
+    for (uint32_t i = 0; i < count; i++) {
+        const rp_batch_request &q = reqs[i];
+        if (q.elem_bytes != eb || q.n >= (1ull << 32))
+            return RP_EINVAL;
+        const int rc = validate(q.A, q.n, q.elem_bytes, q.eps);
+        if (rc != RP_OK)
+            return rc;
+        if (q.H != nullptr && (reinterpret_cast<uintptr_t>(q.H) & 7u) != 0)
+            return RP_EINVAL;
+    }
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return RP_EDEVICE;
+    DevInfo di;
+    int rc = device_info(dev, &di);
+    if (rc != RP_OK)
+        return rc;
+    const int ebc = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
+    int occ[4];
+    for (int a = 0; a < 4; a++)
+        occ[a] = di.occ[a][eb_index(ebc)];
+    const GroupFn fn = pick_group_kernel(ebc);
+    int gocc = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &gocc, reinterpret_cast<const void *>(fn), WG, 0) != hipSuccess)
+        return RP_EDEVICE;
+    const uint64_t capacity = (uint64_t)di.cus * (uint64_t)std::max(gocc, 1);
+
+    // Each shuffle is planned exactly as a call of its own would be; the
+    // workgroups of all of them must be resident together.
+    std::vector<Plan> pl(count);
+    std::vector<uint64_t> off(count, 0);
+    uint64_t aux_total = 0, wg_total = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        if (reqs[i].n <= 1)
+            continue;
+        rc = choose_plan(reqs[i].n, eb, reqs[i].eps, di.cus, occ, &pl[i]);
+        if (rc != RP_OK)
+            return rc;
+        if (!pl[i].single && pl[i].M != 1)
+            return RP_EINVAL;
+        off[i] = aux_total;
+        aux_total += pl[i].aux_bytes;
+        if (!pl[i].single)
+            wg_total += pl[i].G;
+    }
+    if (wg_total > capacity)
+        return RP_EINVAL;
+    if (stats)
+        for (uint32_t i = 0; i < count; i++) {
+            std::memset(&stats[i], 0, sizeof(rp_stats));
+            stats[i].aux_bound_words = rp_aux_bound_words(reqs[i].n ? reqs[i].n : 1, reqs[i].eps);
+        }
+    if (aux_total == 0)
+        return RP_OK;
+
+    void *mem = nullptr, *smem = nullptr;
+    if (aux_alloc(&mem, aux_total, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RP_ENOMEM;
+    }
+    if (hipMallocAsync(&smem, (uint64_t)count * S_WORDS * 8, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFreeAsync(mem, stream);
+        return RP_ENOMEM;
+    }
+    auto release = [&]() {
+        (void)hipFreeAsync(smem, stream);
+        return hipFreeAsync(mem, stream);
+    };
+    unsigned char *base = static_cast<unsigned char *>(mem);
+    uint64_t *dstats = static_cast<uint64_t *>(smem);
+    // Shuffles whose bound holds no table (k = 1) run as the sequential
+    // single-lane kernel ahead of the group; the others form the group.
+    GroupParams gp{};
+    std::vector<Params> singles(count);
+    std::vector<uint32_t> slot_of(count, GROUP_MAX);
+    std::vector<bool> single(count, false);
+    uint32_t first = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        if (reqs[i].n <= 1)
+            continue;
+        rp_stats hs;
+        fill_host_stats(pl[i], &hs);
+        const uint64_t words32 = pl[i].aux_bytes / 4;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(
+            8192, std::max<uint64_t>(64, words32 / (256 * 16)));
+        rp_init_kernel<<<blocks, 256, 0, stream>>>(reinterpret_cast<uint32_t *>(base + off[i]),
+                                                   words32, dstats + (uint64_t)i * S_WORDS, hs);
+        Params &p = pl[i].single ? singles[i] : gp.g[gp.count];
+        setup_params(p, pl[i], RP_VARIANT_FINAL, false, reqs[i].A, reqs[i].n, eb, reqs[i].H,
+                     reqs[i].seed, base + off[i], dstats + (uint64_t)i * S_WORDS);
+        if (pl[i].single) {
+            single[i] = true;
+            continue;
+        }
+        p.wg_first = first;
+        p.wg_count = pl[i].G;
+        first += pl[i].G;
+        slot_of[i] = gp.count++;
+    }
+    if (hipGetLastError() != hipSuccess) {
+        (void)release();
+        return RP_EDEVICE;
+    }
+    // Explicit targets: reject the whole group if any H[i] > i, before
+    // anything moves.
+    auto err_of = [&](uint32_t i) {
+        return single[i] ? singles[i].err : gp.g[slot_of[i]].err;
+    };
+    bool any_h = false;
+    for (uint32_t i = 0; i < count; i++)
+        if (reqs[i].H != nullptr && reqs[i].n > 1) {
+            any_h = true;
+            rp_check_targets_kernel<<<1024, 256, 0, stream>>>(reqs[i].H, reqs[i].n, err_of(i));
+        }
+    if (any_h) {
+        uint32_t bad = 0;
+        for (uint32_t i = 0; i < count && rc == RP_OK; i++) {
+            if (reqs[i].H == nullptr || reqs[i].n <= 1)
+                continue;
+            uint32_t e = 0;
+            if (hipMemcpyAsync(&e, err_of(i), 4, hipMemcpyDeviceToHost, stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                rc = RP_EDEVICE;
+            bad |= e;
+        }
+        if (rc == RP_OK && hipGetLastError() != hipSuccess)
+            rc = RP_EDEVICE;
+        if (rc != RP_OK || bad != 0) {
+            (void)release();
+            return rc != RP_OK ? rc : RP_EINVAL;
+        }
+    }
+    for (uint32_t i = 0; i < count; i++)
+        if (single[i])
+            rp_single_kernel<<<1, 64, 0, stream>>>(singles[i]);
+    if (hipGetLastError() != hipSuccess) {
+        (void)release();
+        return RP_EDEVICE;
+    }
+    void *args[] = {&gp};
+    if (gp.count > 0 &&
+        hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3((uint32_t)wg_total),
+                                   dim3(WG), args, 0, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)release();
+        return RP_EDEVICE;
+    }
+    if (stats)
+        for (uint32_t i = 0; i < count; i++)
+            if (reqs[i].n > 1 &&
+                hipMemcpyAsync(&stats[i], dstats + (uint64_t)i * S_WORDS, sizeof(rp_stats),
+                               hipMemcpyDeviceToHost, stream) != hipSuccess) {
+                (void)release();
+                return RP_EDEVICE;
+            }
+    if (release() != hipSuccess)
+        return RP_EDEVICE;
+    return RP_OK;
 }
 
 int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,

@@ -220,10 +220,12 @@ def test_partial_wait_covers_reservations(tmp_path):
     its N record loads in flight; that is only safe if, on every path, the N
     most recent vector memory instructions before the wait are those loads
     (so every reservation atomic and window clear, issued earlier, has
-    completed).  Checked on every instance of the single-shuffle kernel."""
+    completed).  Checked on every instance of the single-shuffle kernel and
+    of its group form."""
     src = [s for s in rpbuild.SRCS if os.path.basename(s) == "rp.hip"][0]
     funcs = _functions(_assembly(src, tmp_path))
-    kernels = {n: b for n, b in funcs.items() if "rp_rounds_kernel" in n}
+    kernels = {n: b for n, b in funcs.items()
+               if "rp_rounds_kernel" in n or "rp_rounds_group_kernel" in n}
     assert kernels
     with_wait = 0
     for name, body in kernels.items():
