@@ -40,7 +40,8 @@ constexpr int N_SMALL_STREAMS = 2;
 constexpr int N_LARGE_STREAMS = 2;
 constexpr int N_STREAMS = N_SMALL_STREAMS + N_LARGE_STREAMS;
 constexpr uint32_t PLAIN_AHEAD = 64;   // plain mode: requests enqueued ahead
-constexpr size_t ALONE_QUEUE = 4;      // large_alone: batch beyond this many waiting
+constexpr size_t ALONE_QUEUE = 8;      // large_alone: batch beyond this many waiting
+constexpr size_t GROUP_MAX = 8;        // shuffles one rp_shuffle_group call takes
 
 uint64_t now_ns()
 {
@@ -151,6 +152,7 @@ struct StreamBufs {                     // reused fill descriptors per stream
 struct Server {
     rp_server_config cfg{};
     int device = 0;
+    uint32_t cus = 1;                   // compute units of the device
     unsigned char *base = nullptr;
     rpserve::Arena arena;
     hipStream_t streams[N_STREAMS] = {};
@@ -297,11 +299,12 @@ bool reap(Server &s)
     for (size_t li = 0; li < s.inflight.size();) {
         Launch &L = s.inflight[li];
         bool finished = false;
-        if (L.done_ev) {   // one rp_shuffle_inplace call (plain mode, or alone)
+        if (L.done_ev) {   // rp_shuffle_inplace (plain mode, alone) or rp_shuffle_group
             const hipError_t e = hipEventQuery(L.done_ev);
             if (e == hipSuccess || e != hipErrorNotReady) {
                 std::lock_guard<std::mutex> lk(s.mu);
-                mark_done(s, L.tickets[0], e == hipSuccess ? RP_OK : RP_EDEVICE);
+                for (uint64_t t : L.tickets)
+                    mark_done(s, t, e == hipSuccess ? RP_OK : RP_EDEVICE);
                 finished = true;
             }
         } else {
@@ -437,13 +440,42 @@ int free_stream(const Server &s, int cls)
     return -1;
 }
 
-// One admitted large request alone on stream `si`, with the single-instance
-// kernel: all compute units work on it (its rounds are grid-wide) instead of
-// one workgroup.  Completion is an event recorded after the call.
+// The oldest admitted large requests on stream `si`, each with the
+// workgroups a call of its own gets (its rounds grid-wide among them)
+// instead of one workgroup: as many of them (of the oldest one's record size,
+// at most GROUP_MAX) as fit one cooperative launch side by side -- their
+// planned grids together within the compute units, so that the launch is
+// always accepted -- in one rp_shuffle_group call, or one alone through
+// rp_shuffle_inplace.  Completion is an event recorded after the call.
 int launch_alone(Server &s, int si)
 {
+    size_t lim = 0;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        const std::deque<uint64_t> &dq = s.admitted[1];
+        if (dq.empty())
+            return RP_PENDING;
+        const uint32_t eb = s.reqs[dq.front()].q.elem_bytes;
+        uint64_t grid = 0;
+        for (uint64_t tk : dq) {
+            const rp_server_request &q = s.reqs[tk].q;
+            if (q.elem_bytes != eb)
+                continue;
+            rp_stats ps{};
+            uint64_t g = s.cus;   // unknown or more than one slot per lane: alone
+            if (rp_plan(q.n, q.elem_bytes, q.eps, s.device, &ps) == RP_OK && ps.grid &&
+                ps.slots_per_lane == 1)
+                g = ps.grid;
+            if (lim > 0 && (grid + g > s.cus || lim == GROUP_MAX))
+                break;
+            grid += g;
+            lim++;
+            if (grid >= s.cus)
+                break;
+        }
+    }
     std::vector<Req *> rs;
-    const std::vector<uint64_t> tickets = take_admitted(s, 1, 1, &rs);
+    const std::vector<uint64_t> tickets = take_admitted(s, 1, std::max<size_t>(lim, 1), &rs);
     if (tickets.empty())
         return RP_PENDING;
     hipStream_t st = s.streams[si];
@@ -451,9 +483,22 @@ int launch_alone(Server &s, int si)
     P.stream = si;
     P.tickets = tickets;
     int rc = fill_arrays(s, si, rs);
-    if (rc == RP_OK)
+    if (rc == RP_OK && rs.size() == 1) {
         rc = rp_shuffle_inplace(s.base + rs[0]->off, rs[0]->q.n, rs[0]->q.elem_bytes, nullptr,
                                 rs[0]->q.seed, rs[0]->q.eps, st, nullptr);
+    } else if (rc == RP_OK) {
+        std::vector<rp_batch_request> br(rs.size());
+        for (size_t i = 0; i < rs.size(); i++) {
+            br[i].A = s.base + rs[i]->off;
+            br[i].n = rs[i]->q.n;
+            br[i].elem_bytes = rs[i]->q.elem_bytes;
+            br[i].reserved = 0;
+            br[i].H = nullptr;
+            br[i].seed = rs[i]->q.seed;
+            br[i].eps = rs[i]->q.eps;
+        }
+        rc = rp_shuffle_group(br.data(), (uint32_t)br.size(), st, nullptr);
+    }
     if (rc == RP_OK && (hipEventCreateWithFlags(&P.done_ev, hipEventDisableTiming) != hipSuccess ||
                         hipEventRecord(P.done_ev, st) != hipSuccess))
         rc = RP_EDEVICE;
@@ -477,9 +522,10 @@ int launch_batched(Server &s, int cls)
     if (si < 0)
         return RP_PENDING;
     if (cls == 1 && s.cfg.large_alone) {
-        // Large requests run alone, one after another in arrival order, as
-        // long as few of them wait; a longer queue (overload) goes out as one
-        // batched launch so that they progress side by side.
+        // Large requests run alone (or a few side by side in one group
+        // launch), one launch after another in arrival order, as long as few
+        // of them wait; a longer queue (overload) goes out as one batched
+        // launch so that they all progress.
         bool alone_running = false;
         for (const Launch &L : s.inflight)
             alone_running = alone_running || (L.done_ev && L.stream >= N_SMALL_STREAMS);
@@ -717,10 +763,14 @@ int rp_server_create(const rp_server_config *cfg, uint64_t *server)
     }
     if (s->cfg.large_log2 == 0)
         s->cfg.large_log2 = 22;
-    if (hipGetDevice(&s->device) != hipSuccess) {
+    int cus = 0;
+    if (hipGetDevice(&s->device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) !=
+            hipSuccess) {
         delete s;
         return RP_EDEVICE;
     }
+    s->cus = (uint32_t)std::max(cus, 1);
     if (hipMalloc(reinterpret_cast<void **>(&s->base), s->cfg.mem_budget_bytes) != hipSuccess) {
         (void)hipGetLastError();
         s->base = nullptr;
