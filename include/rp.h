@@ -388,12 +388,14 @@ typedef struct rp_server_config {
     uint32_t tick_us;            /* dispatcher poll interval; 0: 50 */
     uint32_t auto_release;       /* 1: free each array as soon as it is done
                                     (results are not kept) */
-    uint32_t large_alone;        /* 1: run large requests one at a time, in
-                                    arrival order, each alone with
-                                    rp_shuffle_inplace (every compute unit
-                                    works on it) instead of in one workgroup
-                                    of a batched launch; when more than 4
-                                    wait, batch them */
+    uint32_t large_alone;        /* 1: run large requests, in arrival
+                                    order, on the workgroups a call of their
+                                    own gets instead of in one workgroup of a
+                                    batched launch: as many as fit one
+                                    cooperative launch together in one
+                                    rp_shuffle_group call (or one alone with
+                                    rp_shuffle_inplace), launch after launch;
+                                    when more than 8 wait, batch them */
     rp_batch_schedule schedule;  /* small requests' schedule; all zero: 1024-lane
                                     workgroups, two per compute unit, the
                                     shortest launches (lowest latency) */
