@@ -288,20 +288,29 @@ int rp_batch_release(uint64_t batch_id);
  * request whose bound holds no table (k = 1) runs as the sequential loop
  * ahead of the group, as it would alone.
  *   reqs    host array of count requests (fields as for rp_batch_submit),
- *           count <= 8, one elem_bytes for all.
+ *           count <= 16, one elem_bytes for all.
  *   stream  hipStream_t (as void*), or NULL.  Stream-ordered.
  *   stats   host array of count rp_stats, filled when the stream reaches the
  *           end of the call, or NULL.
  * Errors: RP_EINVAL for a request rp_shuffle_inplace would reject, mixed
- * record sizes, count > 8, a request whose plan needs more than one swap
- * slot per lane (it fills the device by itself), groups that together do not
- * fit one launch on the device, or (explicit targets) some H[i] > i in any
+ * record sizes, count > 16, a request whose plan needs more than one swap
+ * slot per lane (it fills the device by itself), groups whose planned grids
+ * (rp_plan's grid) add up to more than rp_group_capacity, or (explicit
+ * targets) some H[i] > i in any
  * request (checked first; the call then waits for the stream).  RP_ENOMEM,
  * RP_EDEVICE.  Every A is untouched whenever an error is returned.
  * rp_last_call_aux_bytes reports the sum over the group.
  */
 int rp_shuffle_group(const rp_batch_request *reqs, uint32_t count, void *stream,
                      rp_stats *stats);
+
+/*
+ * The most workgroups the planned grids of one rp_shuffle_group call may add
+ * up to on `device` for records of elem_bytes (the workgroups of its kernel
+ * that can be resident at once).  Host only; *workgroups receives it.
+ * RP_EINVAL for a bad elem_bytes or NULL; RP_EDEVICE.
+ */
+int rp_group_capacity(uint32_t elem_bytes, int device, uint64_t *workgroups);
 
 /* ------------------------------------------------------------------------
  * List ranking by in-place list contraction (Section 4.2: list contraction
@@ -395,7 +404,7 @@ typedef struct rp_server_config {
                                     cooperative launch together in one
                                     rp_shuffle_group call (or one alone with
                                     rp_shuffle_inplace), launch after launch;
-                                    when more than 8 wait, batch them */
+                                    when more than 16 wait, batch them */
     rp_batch_schedule schedule;  /* small requests' schedule; all zero: 1024-lane
                                     workgroups, two per compute unit, the
                                     shortest launches (lowest latency) */

@@ -339,6 +339,22 @@ def rp_shuffle_group(arrays, *, seeds=None, H=None, eps: float = 0.5, stream=Non
     return [_stats_dict(st[i]) for i in range(len(arrays))]
 
 
+def rp_group_capacity(elem_bytes: int, device: int = 0) -> int:
+    """The most workgroups the planned grids of one rp_shuffle_group call may
+    add up to (host query)."""
+    L = lib()
+    if not getattr(L, "_gcap_ready", False):
+        L.rp_group_capacity.restype = ctypes.c_int
+        L.rp_group_capacity.argtypes = [ctypes.c_uint32, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L._gcap_ready = True
+    out = ctypes.c_uint64(0)
+    rc = L.rp_group_capacity(elem_bytes, device, ctypes.byref(out))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_group_capacity")
+    return int(out.value)
+
+
 def rp_batch_requests(arrays, *, seeds=None, H=None, eps: float = 0.5):
     """Marshal the request descriptors once, for repeated submits of the same
     arrays (pass the result as `requests=` to rp_batch_submit)."""

@@ -559,7 +559,7 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 // Several independent shuffles in one cooperative launch: shuffle i runs on
 // workgroups [g[i].wg_first, g[i].wg_first + g[i].wg_count) with its own
 // auxiliary words, its rounds synchronised among those workgroups only.
-constexpr uint32_t GROUP_MAX = 8;
+constexpr uint32_t GROUP_MAX = 16;
 struct GroupParams {
     uint32_t count;
     uint32_t pad;
@@ -1169,6 +1169,23 @@ int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
 uint64_t rp_last_call_aux_bytes(void)
 {
     return g_ledger.device_bytes + g_ledger.lds_bytes;
+}
+
+int rp_group_capacity(uint32_t elem_bytes, int device, uint64_t *workgroups)
+{
+    if (workgroups == nullptr || elem_bytes == 0 || (elem_bytes & 3u) != 0 || elem_bytes > 256)
+        return RP_EINVAL;
+    DevInfo di;
+    int rc = device_info(device, &di);
+    if (rc != RP_OK)
+        return rc;
+    const int ebc = (elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16) ? (int)elem_bytes : 0;
+    int gocc = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &gocc, reinterpret_cast<const void *>(pick_group_kernel(ebc)), WG, 0) != hipSuccess)
+        return RP_EDEVICE;
+    *workgroups = (uint64_t)di.cus * (uint64_t)std::max(gocc, 1);
+    return RP_OK;
 }
 
 int rp_shuffle_group(const rp_batch_request *reqs, uint32_t count, void *stream_,

@@ -40,8 +40,8 @@ constexpr int N_SMALL_STREAMS = 2;
 constexpr int N_LARGE_STREAMS = 2;
 constexpr int N_STREAMS = N_SMALL_STREAMS + N_LARGE_STREAMS;
 constexpr uint32_t PLAIN_AHEAD = 64;   // plain mode: requests enqueued ahead
-constexpr size_t ALONE_QUEUE = 8;      // large_alone: batch beyond this many waiting
-constexpr size_t GROUP_MAX = 8;        // shuffles one rp_shuffle_group call takes
+constexpr size_t ALONE_QUEUE = 16;     // large_alone: batch beyond this many waiting
+constexpr size_t GROUP_MAX = 16;       // shuffles one rp_shuffle_group call takes
 
 uint64_t now_ns()
 {
@@ -444,7 +444,7 @@ int free_stream(const Server &s, int cls)
 // workgroups a call of its own gets (its rounds grid-wide among them)
 // instead of one workgroup: as many of them (of the oldest one's record size,
 // at most GROUP_MAX) as fit one cooperative launch side by side -- their
-// planned grids together within the compute units, so that the launch is
+// planned grids together within rp_group_capacity, so that the launch is
 // always accepted -- in one rp_shuffle_group call, or one alone through
 // rp_shuffle_inplace.  Completion is an event recorded after the call.
 int launch_alone(Server &s, int si)
@@ -456,21 +456,23 @@ int launch_alone(Server &s, int si)
         if (dq.empty())
             return RP_PENDING;
         const uint32_t eb = s.reqs[dq.front()].q.elem_bytes;
+        uint64_t cap = s.cus;   // one workgroup per unit always fits
+        (void)rp_group_capacity(eb, s.device, &cap);
         uint64_t grid = 0;
         for (uint64_t tk : dq) {
             const rp_server_request &q = s.reqs[tk].q;
             if (q.elem_bytes != eb)
                 continue;
             rp_stats ps{};
-            uint64_t g = s.cus;   // unknown or more than one slot per lane: alone
+            uint64_t g = cap;   // unknown or more than one slot per lane: alone
             if (rp_plan(q.n, q.elem_bytes, q.eps, s.device, &ps) == RP_OK && ps.grid &&
                 ps.slots_per_lane == 1)
                 g = ps.grid;
-            if (lim > 0 && (grid + g > s.cus || lim == GROUP_MAX))
+            if (lim > 0 && (grid + g > cap || lim == GROUP_MAX))
                 break;
             grid += g;
             lim++;
-            if (grid >= s.cus)
+            if (grid >= cap)
                 break;
         }
     }

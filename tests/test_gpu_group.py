@@ -94,12 +94,38 @@ def test_group_rejections():
     b = workloads.identity(1000, torch.int32, DEV)
     with pytest.raises(rp.RpError):           # mixed record sizes
         rp.rp_shuffle_group([a, b], seeds=[1, 2], eps=0.5)
-    many = [workloads.identity(100, torch.int64, DEV) for _ in range(9)]
-    with pytest.raises(rp.RpError):           # more than 8
-        rp.rp_shuffle_group(many, seeds=list(range(9)), eps=0.5)
+    many = [workloads.identity(100, torch.int64, DEV) for _ in range(17)]
+    with pytest.raises(rp.RpError):           # more than 16
+        rp.rp_shuffle_group(many, seeds=list(range(17)), eps=0.5)
     big = workloads.identity(1 << 22, torch.int64, DEV)
     with pytest.raises(rp.RpError):           # needs more than one slot per lane
         rp.rp_shuffle_group([big], seeds=[1], eps=0.05)
     torch.cuda.synchronize()
     assert torch.equal(a.cpu(), torch.arange(1000, dtype=torch.int64))
     assert torch.equal(big[:10].cpu(), torch.arange(10, dtype=torch.int64))
+
+
+def test_group_of_sixteen_within_capacity():
+    sizes = [(1 << 16) + 17 * i for i in range(16)]
+    seeds = [100 + i for i in range(16)]
+    arrays = [workloads.identity(n, torch.int64, DEV) for n in sizes]
+    stats = rp.rp_shuffle_group(arrays, seeds=seeds, eps=0.5)
+    for A, n, sd, st in zip(arrays, sizes, seeds, stats):
+        assert st["status"] == 0 and np.array_equal(A.cpu().numpy(), _want(n, sd))
+
+
+def test_group_beyond_capacity_is_refused():
+    cap = rp.rp_group_capacity(8)
+    n, eps = 1 << 22, 0.35
+    g = rp.rp_plan(n, 8, eps, device=0)["grid"]
+    count = -(-(cap + 1) // g)
+    if count > 16:
+        pytest.skip(f"capacity {cap} not reachable with 16 requests of grid {g}")
+    arrays = [workloads.identity(n, torch.int64, DEV) for _ in range(count)]
+    with pytest.raises(rp.RpError) as e:
+        rp.rp_shuffle_group(arrays, seeds=list(range(count)), eps=eps)
+    assert e.value.code == rp.RP_EINVAL
+    torch.cuda.synchronize()
+    assert all(torch.equal(A[:8].cpu(), torch.arange(8, dtype=torch.int64)) for A in arrays)
+    del arrays
+    torch.cuda.empty_cache()
