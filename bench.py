@@ -51,6 +51,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+KERNEL_NAME = "rp_rounds_kernel"
 WORKLOAD = {"n": 1 << 30, "elem_bytes": 8, "eps": 0.5, "seed": 1}
 BATCH = {"count": 4096, "lo_log2": 8, "hi_log2": 20, "size_seed": 12345,
          "seed_base": 1000, "eps": 0.5}
@@ -85,20 +86,50 @@ def _traffic_bytes(workload: str = "plain"):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(log):
-    """Time the CPU oracle (sequential Knuth shuffle, one core) on a sample."""
-    import numpy as np
-    import oracle
-    n = 1 << 27
-    A = np.arange(n, dtype=np.int64)
-    t0 = time.perf_counter()
-    oracle.knuth_shuffle_seed(A, WORKLOAD["seed"])
-    dt = time.perf_counter() - t0
-    log(f"cpu oracle: n=2^27 int64 in {dt:.2f} s")
-    return {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": "full sequential Knuth shuffle (seed mode, targets drawn "
-                      "inline) of a 2^27-element int64 array (1 GiB) on one "
-                      "host core; per-element rate quoted for the 2^30 workload"}
+def host_info():
+    """CPU model and the cores this process may use, for the baseline record."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+class OracleRun:
+    """The sequential Knuth shuffle of the headline input (n = 2^30 int64,
+    A[i] = i, seed mode) on one host core, in a thread of its own (the C
+    oracle runs outside the interpreter lock), so that the GPU steps proceed
+    meanwhile.  Its result is the full-array parity reference and its time is
+    the CPU baseline."""
+
+    def __init__(self, n, seed, log):
+        import threading
+        import numpy as np
+        self.n, self.seed, self.log = n, seed, log
+        self.want = np.arange(n, dtype=np.int64)
+        self.seconds = None
+        self._th = threading.Thread(target=self._run, daemon=True)
+        self._th.start()
+
+    def _run(self):
+        import oracle
+        t0 = time.perf_counter()
+        oracle.knuth_shuffle_seed(self.want, self.seed)
+        self.seconds = time.perf_counter() - t0
+        self.log(f"cpu oracle: n={self.n} int64 in {self.seconds:.2f} s (one core)")
+
+    def join(self):
+        self._th.join()
+        return self.want
 
 
 def main():
@@ -107,13 +138,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload",
-                    choices=("plain", "batch", "serve", "ablation", "list", "scale"),
+                    choices=("plain", "batch", "serve", "ablation", "list", "scale", "floor"),
                     default="plain")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve workload: seconds of arrivals per rate")
     ap.add_argument("--rates", default="50,200,1000",
                     help="serve workload: arrival rates (requests/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=200.0,
+                    help="plain workload: arrival rate of the short served leg")
+    ap.add_argument("--serve-duration", type=float, default=8.0,
+                    help="plain workload: seconds of arrivals of the served leg (0: none)")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch workload: skip the one-launch-per-instance comparison")
@@ -139,8 +174,58 @@ def main():
         run_list(args, log)
     elif args.workload == "scale":
         run_scale(args, log)
+    elif args.workload == "floor":
+        run_floor(args, log)
     else:
         run_plain(args, log)
+
+
+def random_access_floor(rp, A, eb, stream, log, reps=3):
+    """Median time of the shuffle's data movement alone (rp_probe_random_rmw:
+    every swap's two reads and two writes, no reservation) on A, which it
+    leaves scrambled."""
+    import torch
+    ts = []
+    for r in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rp.rp_probe_random_rmw(A, seed=1 + r, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = sorted(ts)[len(ts) // 2]
+    n = A.shape[0]
+    log(f"random-access floor: n={n} x {eb} B in {ms:.2f} ms "
+        f"({4 * eb * n / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic)")
+    return ms
+
+
+def serve_leg(rp, rate, duration, log):
+    """A short served run at one Poisson rate, batched server against one
+    plain launch per request, on the same trace (the serving workload's
+    request mix)."""
+    import numpy as np
+    from paper_2103_01216_amd import workloads
+    count = max(1, int(rate * duration))
+    gaps = np.random.default_rng(SERVE["arrival_seed"]).exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps)
+    sizes = workloads.batch_sizes(count, SERVE["lo_log2"], SERVE["hi_log2"], SERVE["size_seed"])
+    seeds = [SERVE["seed_base"] + i for i in range(count)]
+    rec = {"rate_per_s": rate, "duration_s": duration, "requests": count,
+           "offered_elements_per_s": float(sizes.sum()) / float(arrivals[-1]),
+           "request_sizes": "n=floor(2^U), U~Uniform[10,26), int64, eps=0.5"}
+    for name, mode in (("batched", rp.RP_SERVE_BATCHED), ("plain", rp.RP_SERVE_PLAIN)):
+        lats, elems, span, unfinished, st = _replay(rp, mode, arrivals, sizes, seeds, log,
+                                                    drain_s=duration)
+        lat_ms = np.array(lats) * 1e3
+        rec[name] = {"elements_per_s": elems / span,
+                     "p50_ms": float(np.percentile(lat_ms, 50)),
+                     "p99_ms": float(np.percentile(lat_ms, 99)),
+                     "completed": count - unfinished, "unfinished": unfinished}
+        log(f"served {rate:g}/s {name}: {elems / span:.3g} elements/s, "
+            f"p50 {rec[name]['p50_ms']:.2f} ms, p99 {rec[name]['p99_ms']:.2f} ms, "
+            f"unfinished {unfinished}")
+    return rec
 
 
 def run_plain(args, log):
@@ -153,37 +238,28 @@ def run_plain(args, log):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    A = torch.arange(n, dtype=torch.int64, device=dev)
+    A = torch.empty(n, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     log(f"allocated A: n=2^30 int64 ({A.numel() * 8 / 2**30:.0f} GiB)")
+    floor_ms = random_access_floor(rp, A, eb, stream, log)
+    A.copy_(torch.arange(n, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
 
     stats = None
     parity = {"checked": False}
+    oracle_run = None
+    got_host = None
     for w in range(warmup):
         stats = rp.rp_shuffle_inplace(A, seed=WORKLOAD["seed"] + w, eps=eps,
                                       stream=stream).get()
         log(f"warmup {w}: rounds={stats['rounds']} k={stats['k']} "
-            f"aux={stats['aux_words']}/{stats['aux_bound_words']} words")
-        if w == 0 and not args.no_check:
-            import oracle
-            seen = torch.zeros(n, dtype=torch.bool, device=dev)
-            seen[A] = True
-            perm_ok = bool(seen.all())
-            del seen
-            rng = np.random.default_rng(7)
-            pos = np.unique(np.concatenate([[0, 1, n - 2, n - 1],
-                                            rng.integers(0, n, 1024)]))
-            t0 = time.perf_counter()
-            src = oracle.sample_sources(n, pos, seed=WORKLOAD["seed"])
-            got = A[torch.from_numpy(pos.astype(np.int64)).to(dev)].cpu().numpy()
-            exact = bool(np.array_equal(got, src.astype(np.int64)))
-            log(f"parity: permutation={perm_ok} sampled_exact={exact} "
-                f"({len(pos)} positions, oracle {time.perf_counter() - t0:.1f} s)")
-            parity = {"checked": True, "permutation": perm_ok,
-                      "sampled_positions_exact": exact, "positions": int(len(pos))}
-            if not (perm_ok and exact):
-                log("PARITY FAILURE")
-                sys.exit(1)
+            f"aux={stats['aux_words']}/{stats['aux_bound_words']} words "
+            f"inflight={stats['inflight_words']} words")
+        if w == 0 and not (args.no_check and args.no_cpu_baseline):
+            # The whole output of the first step comes back to the host and is
+            # compared with the oracle's whole output once the oracle is done.
+            oracle_run = OracleRun(n, WORKLOAD["seed"], log)
+            got_host = A.cpu().numpy()
 
     # Timed region: K steps, HIP events on the stream the kernels run on.
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -201,9 +277,37 @@ def run_plain(args, log):
     ms = sum(step_ms) / len(step_ms)
     value = n * args.steps / wall
     log(f"steps ms: {', '.join(f'{x:.2f}' for x in step_ms)}; wall {wall:.3f} s")
+    del A
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if oracle_run is not None:
+        want = oracle_run.join()
+        if not args.no_check:
+            exact = bool(np.array_equal(got_host, want))
+            mism = 0 if exact else int(np.count_nonzero(got_host != want))
+            log(f"parity: whole array of the first step vs the oracle: "
+                f"{'equal' if exact else f'{mism} positions differ'}")
+            parity = {"checked": True, "whole_array_equal": exact, "positions": n,
+                      "mismatches": mism}
+            if not exact:
+                log("PARITY FAILURE")
+                sys.exit(1)
+        cpu = {"value": n / oracle_run.seconds, "unit": "elements/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "the whole headline input: sequential Knuth shuffle (seed mode, "
+                         "targets drawn inline) of n=2^30 int64 A[i]=i, seed 1, on one "
+                         "host core, run beside the GPU steps",
+               "seconds": oracle_run.seconds, **host_info()}
+        del want, got_host
+
+    served = None
+    if args.serve_duration > 0:
+        served = serve_leg(rp, args.serve_rate, args.serve_duration, log)
 
     alg_bytes = 4 * eb * n                      # A[s], A[H[s]]: read + write
     achieved = alg_bytes / (ms * 1e-3) / 1e9    # GB/s over the kernel's time
+    floor_gbps = alg_bytes / (floor_ms * 1e-3) / 1e9
     traffic = _traffic_bytes()
     out = {
         "metric": "in-place shuffle elements/s at n=2^30 int64 (% HBM peak)",
@@ -222,8 +326,12 @@ def run_plain(args, log):
                                "initially, H[i]=splitmix64(seed^i) mod (i+1), eps=0.5",
                    "n": n, "elem_bytes": eb, "eps": eps,
                    "k": stats["k"], "rounds": stats["rounds"],
+                   "attempts": stats["attempts"], "retries": stats["retries"],
                    "aux_words": stats["aux_words"],
                    "aux_bound_words": stats["aux_bound_words"],
+                   "inflight_words": stats["inflight_words"],
+                   "k_over_bound": stats["k"] / stats["aux_bound_words"],
+                   "throttled_rounds": stats["throttled_rounds"],
                    "grid": stats["grid"], "slots_per_lane": stats["slots_per_lane"],
                    "round_us": ms * 1e3 / max(1, stats["rounds"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
@@ -232,14 +340,79 @@ def run_plain(args, log):
                      "traffic_gbps": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
                      "traffic_frac": (traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS)
                      if traffic else None,
-                     "kernel": "rp_rounds_kernel", "kernel_ms_events": ms,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "kernel": KERNEL_NAME, "kernel_ms_events": ms,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "random_access_floor_ms": floor_ms,
+                     "random_access_floor_gbps": floor_gbps,
+                     "frac_of_random_access_floor": floor_ms / ms},
         "parity": parity,
     }
-    if not args.no_cpu_baseline:
+    if served is not None:
+        out["served"] = served
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def run_floor(args, log):
+    """Ceilings the shuffle's time is compared with: the random-access floor
+    of its data movement at the two headline shapes, a streaming copy, the
+    flag barrier of a round, and device-scope atomics into a table of the
+    headline's size."""
+    import torch
+    import paper_2103_01216_amd as rp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for name, n, eb in (("n2p30_int64", 1 << 30, 8), ("n2p26_rec64", 1 << 26, 64)):
+        A = torch.zeros((n, eb // 8), dtype=torch.int64, device=dev)
+        ms = random_access_floor(rp, A, eb, stream, log, reps=5)
+        res[name] = {"ms": ms, "swaps_per_s": n / (ms * 1e-3),
+                     "algorithmic_gbps": 4 * eb * n / (ms * 1e-3) / 1e9}
         del A
         torch.cuda.empty_cache()
-        out["cpu_baseline"] = cpu_baseline(log)
+    nbytes = 4 << 30
+    src = torch.zeros(nbytes // 8, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    ts = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rp.rp_probe_copy(dst, src, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = sorted(ts)[2]
+    res["copy_4GiB"] = {"ms": ms, "gbps": 2 * nbytes / (ms * 1e-3) / 1e9}
+    log(f"copy 4 GiB: {ms:.2f} ms, {2 * nbytes / (ms * 1e-3) / 1e9:.0f} GB/s read+write")
+    del src, dst
+    torch.cuda.empty_cache()
+    bar = {}
+    for g in (2, 64, 228, 456, 1024):
+        us = rp.rp_probe_barrier(g, 20000, stream=stream)
+        bar[str(g)] = us
+        log(f"flag barrier on {g} workgroups: {us:.2f} us")
+    res["barrier_us_by_grid"] = bar
+    T, grid = 57440, 228
+    ns_tp = rp.rp_probe_atomics(T, grid, 256, False, stream=stream)
+    ns_lat = rp.rp_probe_atomics(T, grid, 256, True, stream=stream)
+    ops = grid * 256 * 256
+    res["atomics"] = {"table_slots": T, "lanes": grid * 256, "per_lane": 256,
+                      "throughput_per_s": ops / (ns_tp * 1e-9),
+                      "chained_ns_per_op": ns_lat / 256}
+    log(f"atomic max into {T} slots: {ops / (ns_tp * 1e-9):.3g}/s in flight, "
+        f"{ns_lat / 256:.0f} ns each when chained")
+    out = {"metric": "device ceilings for the shuffle (random-access floor, copy, barrier, atomics)",
+           "value": res["n2p30_int64"]["algorithmic_gbps"], "unit": "GB/s", "n_gpus": 1,
+           "steps": 5, "warmup": 0, "ms_per_step": res["n2p30_int64"]["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "probes: swap data movement of n=2^30 int64 and n=2^26 x 64 B "
+                                  "(seed-mode targets, no reservation), 4 GiB copy, flag "
+                                  "barriers, atomic max into 57440 slots",
+                      "results": res}}
     print(json.dumps(out), flush=True)
 
 

@@ -67,6 +67,18 @@ extern "C" {
  *   grid, slots_per_lane, table_slots   launch shape and number of 32-bit
  *                     slots of the hashed reservation array
  *   status            RP_OK, or RP_ETIMEOUT if the device watchdog fired
+ *   inflight_words    state the k active swaps hold in registers, in 8-byte
+ *                     words: per swap its source and target (4 bytes each)
+ *                     and, for records of 4, 8 or 16 bytes, both records
+ *                     (read ahead of the decision); other record sizes are
+ *                     moved after the decision and hold none.  Not device
+ *                     memory and not part of aux_words; reported so that the
+ *                     whole working set of a round can be compared with the
+ *                     bound (Section 4.1 keeps the prefix's H values inside
+ *                     its O(n^(1-eps)) table).
+ *   throttled_rounds  rounds whose refill was cut short so that every active
+ *                     swap's rank (its distance above the round's lowest
+ *                     fresh index) fits the 24-bit priority field
  */
 typedef struct rp_stats {
     uint64_t k;
@@ -81,6 +93,8 @@ typedef struct rp_stats {
     uint64_t slots_per_lane;
     uint64_t table_slots;
     int64_t status;
+    uint64_t inflight_words;
+    uint64_t throttled_rounds;
 } rp_stats;
 
 /*
@@ -191,6 +205,49 @@ uint64_t rp_last_call_aux_bytes(void);
  */
 int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
                     uint64_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement probes: the device costs a round is made of, measured in
+ * isolation, to compare the shuffle's time with.  Section 7.4 counts the
+ * sequential and random accesses a swap makes per round; these give the
+ * price of each kind on this device.  None of them is part of the shuffle.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * The data movement of a shuffle with nothing else: for every s < n (in no
+ * particular order, unsynchronised) read A[s] and A[H[s]], H[s] the seed-mode
+ * target, and write them back exchanged.  Swaps that share a location race,
+ * so A afterwards is NOT a permutation of its input: re-initialise it.
+ * Moves the shuffle's algorithmic bytes (4 * elem_bytes per element) at its
+ * real addresses.  elem_bytes 4, 8, 16 or 64; A aligned to
+ * min(elem_bytes, 16) bytes; n < 2^32.  Stream-ordered, non-blocking; time it
+ * with events.  RP_EINVAL, RP_EDEVICE.
+ */
+int rp_probe_random_rmw(void *A, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                        void *stream);
+
+/* Streaming copy of `bytes` (multiple of 16; both pointers 16-byte aligned,
+ * device) in 16-byte accesses: the bandwidth reference, and the kernel of
+ * known traffic that hardware byte counters are scaled by.  Stream-ordered,
+ * non-blocking.  RP_EINVAL, RP_EDEVICE. */
+int rp_probe_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+
+/* Microseconds per grid-wide flag barrier (the barrier between the phases
+ * of a round) on `grid` workgroups of 256 lanes, averaged over `rounds`
+ * barriers of one cooperative launch.  Allocates its flags, waits for the
+ * stream; *us_per_barrier (host) receives the result.  2 <= grid <= 2048.
+ * RP_EINVAL, RP_ENOMEM, RP_EDEVICE. */
+int rp_probe_barrier(uint32_t grid, uint32_t rounds, void *stream, double *us_per_barrier);
+
+/* Device-scope 32-bit atomic max (the reservation's operation): grid
+ * workgroups of 256 lanes each issue per_lane atomics on pseudo-random slots
+ * of a table of table_slots words, either all in flight at once
+ * (chained = 0: throughput) or each after the previous one returned
+ * (chained = 1: latency).  *ns_total (host) receives the launch's time in
+ * nanoseconds.  Allocates the table, waits for the stream.  RP_EINVAL,
+ * RP_ENOMEM, RP_EDEVICE. */
+int rp_probe_atomics(uint32_t table_slots, uint32_t grid, uint32_t per_lane, int chained,
+                     void *stream, double *ns_total);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent shuffles in one persistent launch.

@@ -32,12 +32,13 @@ _ERRORS = {RP_EINVAL: "RP_EINVAL", RP_ENOMEM: "RP_ENOMEM",
 
 STATS_FIELDS = ("k", "aux_words", "aux_bound_words", "rounds", "attempts",
                 "retries", "max_active", "self_loops", "grid",
-                "slots_per_lane", "table_slots", "status")
+                "slots_per_lane", "table_slots", "status", "inflight_words",
+                "throttled_rounds")
 
 
 class rp_stats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_uint64) for f in STATS_FIELDS[:-1]] + \
-        [("status", ctypes.c_int64)]
+    _fields_ = [(f, ctypes.c_int64 if f == "status" else ctypes.c_uint64)
+                for f in STATS_FIELDS]
 
 
 class RpError(RuntimeError):
@@ -112,12 +113,29 @@ def _record_geometry(A):
     return n, A.element_size() * row
 
 
+# Pinned statistics buffers whose device-to-host copy may still be in flight,
+# each with an event recorded after the copy: the buffer stays referenced
+# until the event has completed, even when the caller drops the PendingStats
+# without calling get() (otherwise the caching host allocator could hand the
+# block to a new pinned tensor before the copy lands in it).
+_inflight_stats = []
+
+
+def _hold_until_done(host, stream):
+    import torch
+    ev = torch.cuda.Event()
+    ev.record(stream)
+    _inflight_stats[:] = [(e, h) for e, h in _inflight_stats if not e.query()]
+    _inflight_stats.append((ev, host))
+
+
 class PendingStats:
     """Statistics of one call, valid once the stream reaches its end."""
 
     def __init__(self, host, stream):
         self._host = host      # pinned torch tensor holding an rp_stats
         self._stream = stream
+        _hold_until_done(host, stream)
 
     def get(self) -> dict:
         self._stream.synchronize()
@@ -203,6 +221,84 @@ def rp_seed_targets(idx, seed: int, stream=None):
     if rc != RP_OK:
         raise RpError(rc, "rp_seed_targets")
     return out
+
+
+# ------------------------------------------------------------ measurement
+
+def _probe_lib():
+    L = lib()
+    if not getattr(L, "_probe_ready", False):
+        u32, u64, vp, i32, dp = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p,
+                                 ctypes.c_int, ctypes.POINTER(ctypes.c_double))
+        L.rp_probe_random_rmw.restype = i32
+        L.rp_probe_random_rmw.argtypes = [vp, u64, u32, u64, vp]
+        L.rp_probe_copy.restype = i32
+        L.rp_probe_copy.argtypes = [vp, vp, u64, vp]
+        L.rp_probe_barrier.restype = i32
+        L.rp_probe_barrier.argtypes = [u32, u32, vp, dp]
+        L.rp_probe_atomics.restype = i32
+        L.rp_probe_atomics.argtypes = [u32, u32, u32, i32, vp, dp]
+        L._probe_ready = True
+    return L
+
+
+def rp_probe_random_rmw(A, *, seed: int = 1, stream=None):
+    """The shuffle's data movement alone (rp_probe_random_rmw of
+    include/rp.h): A is left scrambled, not permuted."""
+    import torch
+    n, eb = _record_geometry(A)
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    rc = _probe_lib().rp_probe_random_rmw(ctypes.c_void_p(A.data_ptr()), n, eb,
+                                          seed & (2**64 - 1),
+                                          ctypes.c_void_p(stream.cuda_stream))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_probe_random_rmw")
+
+
+def rp_probe_copy(dst, src, *, stream=None):
+    """Streaming copy of src's bytes into dst (rp_probe_copy)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device)
+    rc = _probe_lib().rp_probe_copy(ctypes.c_void_p(dst.data_ptr()),
+                                    ctypes.c_void_p(src.data_ptr()), nbytes,
+                                    ctypes.c_void_p(stream.cuda_stream))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_probe_copy")
+
+
+def rp_probe_barrier(grid: int, rounds: int = 20000, stream=None) -> float:
+    """Microseconds per grid-wide flag barrier on `grid` workgroups."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_double(0.0)
+    rc = _probe_lib().rp_probe_barrier(grid, rounds, ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(out))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_probe_barrier")
+    return float(out.value)
+
+
+def rp_probe_atomics(table_slots: int, grid: int, per_lane: int, chained: bool,
+                     stream=None) -> float:
+    """Nanoseconds for grid*256*per_lane device-scope atomic max operations on
+    a table of table_slots words (all in flight, or chained one after the
+    other per lane)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_double(0.0)
+    rc = _probe_lib().rp_probe_atomics(table_slots, grid, per_lane, 1 if chained else 0,
+                                       ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(out))
+    if rc != RP_OK:
+        raise RpError(rc, "rp_probe_atomics")
+    return float(out.value)
 
 
 # ------------------------------------------------------------------ batches
@@ -318,7 +414,7 @@ class Batch:
 
 
 def rp_shuffle_group(arrays, *, seeds=None, H=None, eps: float = 0.5, stream=None):
-    """Up to 8 independent shuffles in one cooperative launch (rp_shuffle_group
+    """Up to 16 independent shuffles in one cooperative launch (rp_shuffle_group
     of include/rp.h), each planned as rp_shuffle_inplace would plan it alone.
     Waits for the stream and returns one statistics dict per array."""
     import torch

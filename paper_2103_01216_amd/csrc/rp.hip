@@ -111,8 +111,9 @@ struct Params {
     uint32_t *bm;
     uint64_t *flags;
     uint32_t *err;
-    uint64_t *dstats;    // rp_stats laid out as 12 x 64-bit words
+    uint64_t *dstats;    // rp_stats laid out as S_WORDS 64-bit words
     uint64_t max_rounds;
+    uint32_t rank_cap;   // refill throttle: active ranks stay below this
     uint32_t variant;    // RP_VARIANT_*: how reservations are held and checked
     uint32_t lds_tab;    // 1: the launch uses the LDS variant of the kernel
     uint64_t *R64;       // RP_VARIANT_LINEAR: one priority word per position
@@ -122,7 +123,9 @@ struct Params {
 
 // rp_stats word indices
 enum { S_K, S_AUX, S_BOUND, S_ROUNDS, S_ATTEMPTS, S_RETRIES, S_MAXACT,
-       S_SELF, S_GRID, S_SLOTS, S_TABLE, S_STATUS, S_WORDS };
+       S_SELF, S_GRID, S_SLOTS, S_TABLE, S_STATUS, S_INFLIGHT, S_THROTTLED,
+       S_WORDS };
+static_assert(S_WORDS * 8 == sizeof(rp_stats), "rp_stats layout");
 
 __device__ __forceinline__ uint32_t target_of(const Params &p, uint32_t s)
 {
@@ -254,7 +257,8 @@ __device__ __forceinline__ void rounds_body(const Params &p)
     }
     uint32_t cursor = p.n;  // fresh swaps are the indices below the cursor
     uint32_t epoch = 0;
-    uint64_t rounds = 0, attempts = 0, retries = 0, selfl = 0, maxact = 0;
+    uint64_t rounds = 0, attempts = 0, retries = 0, selfl = 0, maxact = 0,
+             throttled = 0;
     bool failed = false;
 
     for (;;) {
@@ -333,9 +337,12 @@ __device__ __forceinline__ void rounds_body(const Params &p)
             failed = true;
             break;
         }
-        // Fresh swaps, throttled so that every active rank fits in 24 bits.
-        const uint32_t take = (uint32_t)min<uint64_t>(
-            min<uint64_t>(totF, cursor), (uint64_t)(RANKMAX - agemax));
+        // Fresh swaps, throttled so that every active rank fits in 24 bits
+        // (below rank_cap, which is 2^24 - 1 unless a test lowers it).
+        const uint64_t want = min<uint64_t>(totF, cursor);
+        const uint64_t room = agemax < p.rank_cap ? (uint64_t)(p.rank_cap - agemax) : 0ull;
+        const uint32_t take = (uint32_t)min<uint64_t>(want, room);
+        throttled += take < want ? 1u : 0u;
         const uint32_t cnew = cursor - take;
         const uint32_t par = (uint32_t)(rounds & 1);
         const uint32_t tag = (uint32_t)(rounds % TAG_CYCLE);
@@ -544,6 +551,7 @@ __device__ __forceinline__ void rounds_body(const Params &p)
         if (w == 0) {
             st(&p.dstats[S_ROUNDS], rounds);
             st(&p.dstats[S_MAXACT], maxact);
+            st(&p.dstats[S_THROTTLED], throttled);
         }
         if (failed)
             st(&p.dstats[S_STATUS], (uint64_t)(int64_t)RP_ETIMEOUT);
@@ -604,7 +612,7 @@ __global__ void rp_init_kernel(uint32_t *aux, uint64_t words32, uint64_t *dstats
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (uint64_t i = i0; i < words32; i += (uint64_t)gridDim.x * blockDim.x)
         aux[i] = 0u;
-    if (i0 == 0) {
+    if (i0 == 0 && dstats != nullptr) {
         dstats[S_K] = host.k;
         dstats[S_AUX] = host.aux_words;
         dstats[S_BOUND] = host.aux_bound_words;
@@ -617,6 +625,8 @@ __global__ void rp_init_kernel(uint32_t *aux, uint64_t words32, uint64_t *dstats
         dstats[S_SLOTS] = host.slots_per_lane;
         dstats[S_TABLE] = host.table_slots;
         dstats[S_STATUS] = 0;
+        dstats[S_INFLIGHT] = host.inflight_words;
+        dstats[S_THROTTLED] = 0;
     }
 }
 
@@ -892,10 +902,19 @@ int device_info(int dev, DevInfo *out)
     return RP_OK;
 }
 
+// Register-held state of the active swaps: source and target (4 bytes each)
+// and, for records moved through registers (4, 8, 16 bytes), both records.
+uint64_t inflight_words_for(uint64_t k, int eb_class)
+{
+    const uint64_t per_swap = 8 + 2 * (uint64_t)eb_class;  // eb_class 0: none held
+    return (k * per_swap + 7) / 8;
+}
+
 void fill_host_stats(const Plan &pl, rp_stats *s)
 {
     std::memset(s, 0, sizeof(*s));
     s->k = pl.k;
+    s->inflight_words = inflight_words_for(pl.k, pl.single ? 0 : pl.eb_class);
     s->aux_words = (pl.aux_bytes + 7) / 8;
     s->aux_bound_words = pl.bound;
     s->grid = pl.G;
@@ -983,6 +1002,11 @@ void setup_params(Params &p, const Plan &pl, int variant, bool lds_tab, void *A,
     // reports RP_ETIMEOUT with A holding a permutation of its input.
     const int max_rounds = env_int("RP_MAX_ROUNDS", 0);
     p.max_rounds = max_rounds > 0 ? (uint64_t)max_rounds : n + 64;
+    // RP_RANK_CAP (environment) lowers the refill throttle's rank limit so
+    // that tests can make it engage at small n; any value >= 1 gives the
+    // same permutation.
+    const int rank_cap = env_int("RP_RANK_CAP", 0);
+    p.rank_cap = (rank_cap > 0 && (uint32_t)rank_cap < RANKMAX) ? (uint32_t)rank_cap : RANKMAX;
     p.wg_first = 0;
     p.wg_count = pl.G;
     unsigned char *cur = base;
@@ -1030,8 +1054,17 @@ hipError_t aux_alloc(void **ptr, uint64_t bytes, hipStream_t stream)
     return e;
 }
 
+// The device memory a call works in: obtained per call (hipMallocAsync, freed
+// stream-ordered at its end), or a caller-supplied region that is neither
+// allocated nor freed here (the no-allocation entry point's static scratch).
+struct CallMemory {
+    unsigned char *fixed = nullptr;
+    uint64_t fixed_bytes = 0;
+};
+
 int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, uint64_t seed,
-                 double eps, int variant, void *stream_, rp_stats *stats)
+                 double eps, int variant, void *stream_, rp_stats *stats,
+                 const CallMemory &cm = CallMemory{})
 {
     g_ledger = AuxLedger{};
     int rc = validate(A, n, elem_bytes, eps);
@@ -1073,16 +1106,28 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     const uint64_t tab_bytes = ((uint64_t)pl.T * 4 + 7) / 8 * 8 + 2ull * pl.bmw * 4;
     const uint64_t aux_bytes = lds_tab ? pl.aux_bytes - tab_bytes : pl.aux_bytes;  // multiple of 8
     void *mem = nullptr, *smem = nullptr;
-    if (aux_alloc(&mem, aux_bytes, stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return RP_ENOMEM;
-    }
-    if (hipMallocAsync(&smem, S_WORDS * 8, stream) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFreeAsync(mem, stream);
-        return RP_ENOMEM;
+    if (cm.fixed != nullptr) {
+        // [aux words | statistics record], both inside the fixed region.
+        const uint64_t aux_span = (aux_bytes + 255) / 256 * 256;
+        if (aux_span + S_WORDS * 8 > cm.fixed_bytes)
+            return RP_ENOMEM;
+        mem = cm.fixed;
+        smem = cm.fixed + aux_span;
+        g_ledger.device_bytes += aux_bytes;
+    } else {
+        if (aux_alloc(&mem, aux_bytes, stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return RP_ENOMEM;
+        }
+        if (hipMallocAsync(&smem, S_WORDS * 8, stream) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFreeAsync(mem, stream);
+            return RP_ENOMEM;
+        }
     }
     auto release = [&]() {
+        if (cm.fixed != nullptr)
+            return hipSuccess;
         (void)hipFreeAsync(smem, stream);
         return hipFreeAsync(mem, stream);
     };
@@ -1372,6 +1417,228 @@ int rp_seed_targets(const uint64_t *idx, uint64_t count, uint64_t seed,
     const uint64_t blocks = std::min<uint64_t>(4096, (count + 255) / 256);
     rp_seed_targets_kernel<<<(unsigned)blocks, 256, 0, stream>>>(idx, count, seed, out);
     return hipGetLastError() == hipSuccess ? RP_OK : RP_EDEVICE;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ measurement probes
+//
+// Microbenchmarks of the device costs the rounds are built from: the data
+// movement of the shuffle alone (every swap's two reads and two writes at its
+// real addresses, with no reservation, so the output is not a permutation), a
+// streaming copy, the flag barrier of the rounds kernel, and device-scope
+// atomic max into a reservation-sized table.  They give the ceilings the
+// shuffle's time is compared with; none is used by the shuffle itself.
+
+namespace {
+
+template <int EB>
+__global__ __launch_bounds__(256) void rp_probe_rmw_kernel(unsigned char *A, uint32_t n,
+                                                           uint64_t seed)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        const uint32_t h = seed_target(seed, s);
+        if constexpr (EB == 64) {
+            uint4 *ps = reinterpret_cast<uint4 *>(A) + 4ull * s;
+            uint4 *ph = reinterpret_cast<uint4 *>(A) + 4ull * h;
+            uint4 a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                a[u] = ps[u];
+                b[u] = ph[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                ps[u] = b[u];
+                ph[u] = a[u];
+            }
+        } else {
+            Rec<EB> a, b;
+            a.load(A, s);
+            b.load(A, h);
+            b.store(A, s);
+            a.store(A, h);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void rp_probe_copy_kernel(uint4 *dst, const uint4 *src,
+                                                            uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+// `rounds` flag barriers on the launch's workgroups, each preceded by the
+// same wait for memory operations and workgroup barrier as in the rounds.
+__global__ __launch_bounds__(WG) void rp_probe_barrier_kernel(Params p, uint32_t rounds)
+{
+    __shared__ uint64_t sh_res[5];
+    for (uint32_t r = 0; r < rounds; r++)
+        if (!plain_barrier(p, r + 1, sh_res))
+            return;
+}
+
+// Each lane issues `per_lane` atomic max operations on pseudo-random slots of
+// a `T`-slot table: fire-and-forget (the wave waits for all of them at the
+// end), or each on the result of the previous one (latency).
+__global__ __launch_bounds__(256) void rp_probe_atomic_kernel(uint32_t *tab, uint32_t T,
+                                                              uint32_t per_lane,
+                                                              uint32_t chained, uint32_t *sink)
+{
+    const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t x = id * 0x9E3779B9u + 1u, acc = 0;
+    for (uint32_t j = 0; j < per_lane; j++) {
+        x ^= x << 13;
+        x ^= x >> 17;
+        x ^= x << 5;
+        const uint32_t slot = (uint32_t)(((uint64_t)(x ^ (chained ? acc & 1u : 0u)) * T) >> 32);
+        if (chained)
+            acc += __hip_atomic_fetch_max(&tab[slot], x, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_fetch_max(&tab[slot], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    wait_mem();
+    if (acc == 0xFFFFFFFFu)
+        st(sink, acc);
+}
+
+int probe_time(hipStream_t stream, hipEvent_t a, hipEvent_t b, double *ms)
+{
+    float f = 0;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&f, a, b) != hipSuccess)
+        return RP_EDEVICE;
+    *ms = f;
+    (void)stream;
+    return RP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rp_probe_random_rmw(void *A, uint64_t n, uint32_t elem_bytes, uint64_t seed, void *stream_)
+{
+    if (n == 0)
+        return RP_OK;
+    if (A == nullptr || n >= (1ull << 32) ||
+        !(elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16 || elem_bytes == 64))
+        return RP_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(A) & (elem_bytes >= 16 ? 15u : elem_bytes - 1u)) != 0)
+        return RP_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    int dev = 0;
+    DevInfo di;
+    if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &di) != RP_OK)
+        return RP_EDEVICE;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((uint64_t)di.cus * 8,
+                                                         (n + 255) / 256);
+    unsigned char *a = static_cast<unsigned char *>(A);
+    switch (elem_bytes) {
+    case 4: rp_probe_rmw_kernel<4><<<blocks, 256, 0, stream>>>(a, (uint32_t)n, seed); break;
+    case 8: rp_probe_rmw_kernel<8><<<blocks, 256, 0, stream>>>(a, (uint32_t)n, seed); break;
+    case 16: rp_probe_rmw_kernel<16><<<blocks, 256, 0, stream>>>(a, (uint32_t)n, seed); break;
+    default: rp_probe_rmw_kernel<64><<<blocks, 256, 0, stream>>>(a, (uint32_t)n, seed); break;
+    }
+    return hipGetLastError() == hipSuccess ? RP_OK : RP_EDEVICE;
+}
+
+int rp_probe_copy(void *dst, const void *src, uint64_t bytes, void *stream_)
+{
+    if (bytes == 0)
+        return RP_OK;
+    if (dst == nullptr || src == nullptr || (bytes & 15u) != 0 ||
+        ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) != 0)
+        return RP_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    int dev = 0;
+    DevInfo di;
+    if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &di) != RP_OK)
+        return RP_EDEVICE;
+    const uint64_t n16 = bytes / 16;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((uint64_t)di.cus * 16, (n16 + 255) / 256);
+    rp_probe_copy_kernel<<<blocks, 256, 0, stream>>>(static_cast<uint4 *>(dst),
+                                                     static_cast<const uint4 *>(src), n16);
+    return hipGetLastError() == hipSuccess ? RP_OK : RP_EDEVICE;
+}
+
+int rp_probe_barrier(uint32_t grid, uint32_t rounds, void *stream_, double *us_per_barrier)
+{
+    if (grid < 2 || grid > MAXG || rounds == 0 || us_per_barrier == nullptr)
+        return RP_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    void *mem = nullptr;
+    const uint64_t bytes = 2ull * grid * 8 + 8;
+    if (hipMallocAsync(&mem, bytes, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RP_ENOMEM;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = RP_EDEVICE;
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+        rp_init_kernel<<<64, 256, 0, stream>>>(static_cast<uint32_t *>(mem), bytes / 4,
+                                               nullptr, rp_stats{});
+        Params p{};
+        p.flags = static_cast<uint64_t *>(mem);
+        p.err = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(mem) + 2ull * grid * 8);
+        p.wg_first = 0;
+        p.wg_count = grid;
+        void *args[] = {&p, &rounds};
+        double ms = 0;
+        if (hipGetLastError() == hipSuccess && hipEventRecord(a, stream) == hipSuccess &&
+            hipLaunchCooperativeKernel(reinterpret_cast<const void *>(rp_probe_barrier_kernel),
+                                       dim3(grid), dim3(WG), args, 0, stream) == hipSuccess &&
+            hipEventRecord(b, stream) == hipSuccess && probe_time(stream, a, b, &ms) == RP_OK) {
+            *us_per_barrier = ms * 1e3 / rounds;
+            rc = RP_OK;
+        }
+        (void)hipGetLastError();
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFreeAsync(mem, stream);
+    (void)hipStreamSynchronize(stream);
+    return rc;
+}
+
+int rp_probe_atomics(uint32_t table_slots, uint32_t grid, uint32_t per_lane, int chained,
+                     void *stream_, double *ns_total)
+{
+    if (table_slots == 0 || grid == 0 || per_lane == 0 || ns_total == nullptr)
+        return RP_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    void *mem = nullptr;
+    const uint64_t bytes = (uint64_t)table_slots * 4 + 8;
+    if (hipMallocAsync(&mem, bytes, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RP_ENOMEM;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = RP_EDEVICE;
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+        uint32_t *tab = static_cast<uint32_t *>(mem);
+        rp_init_kernel<<<64, 256, 0, stream>>>(tab, bytes / 4, nullptr, rp_stats{});
+        double ms = 0;
+        if (hipGetLastError() == hipSuccess && hipEventRecord(a, stream) == hipSuccess) {
+            rp_probe_atomic_kernel<<<grid, 256, 0, stream>>>(tab, table_slots, per_lane,
+                                                             chained ? 1u : 0u,
+                                                             tab + table_slots);
+            if (hipGetLastError() == hipSuccess && hipEventRecord(b, stream) == hipSuccess &&
+                probe_time(stream, a, b, &ms) == RP_OK) {
+                *ns_total = ms * 1e6;
+                rc = RP_OK;
+            }
+        }
+        (void)hipGetLastError();
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFreeAsync(mem, stream);
+    (void)hipStreamSynchronize(stream);
+    return rc;
 }
 
 }  // extern "C"

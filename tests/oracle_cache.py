@@ -1,0 +1,27 @@
+"""Whole-array oracle results shared by the full-size GPU parity tests.
+
+The shuffle of the identity array is the permutation itself, and with
+identity input the result does not depend on the element type or on eps, so
+one oracle run per (n, seed) serves every configuration of that size.  The
+last result is kept (the largest is 8 GiB on the host).
+"""
+import functools
+
+import numpy as np
+
+import oracle
+
+
+@functools.lru_cache(maxsize=1)
+def shuffled_identity(n: int, seed: int) -> np.ndarray:
+    """The sequential Knuth shuffle (seed mode) of A[i] = i, as int64."""
+    want = np.arange(n, dtype=np.int64)
+    oracle.knuth_shuffle_seed(want, seed)
+    want.setflags(write=False)
+    return want
+
+
+def device_copy(n: int, seed: int, device):
+    """shuffled_identity(n, seed) as a device int64 tensor."""
+    import torch
+    return torch.from_numpy(shuffled_identity(n, seed)).to(device)

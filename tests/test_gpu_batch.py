@@ -151,17 +151,15 @@ def test_config_4096_log_uniform_2p8_2p20():
         seen = torch.zeros(a.numel(), dtype=torch.bool, device=DEV)
         seen[a.long()] = True
         assert bool(seen.all())
-    # and a spread of them, including the largest, equals the oracle exactly
-    check = sorted(set(list(range(0, 4096, 97)) + [int(np.argmax(sizes))]))
-    for i in check:
+    # and every one of them equals the oracle exactly
+    for i in range(len(sizes)):
         assert np.array_equal(arrays[i].cpu().numpy(), _oracle(int(sizes[i]), seeds[i])), i
 
 
 @pytest.mark.parametrize("lanes", [256, 1024])
 def test_large_request_in_a_batch(lanes):
     """Large requests (k up to 8192 active swaps in a 1024-lane workgroup)
-    run without a rank throttle; checked at sampled positions plus the
-    permutation property."""
+    run without a rank throttle; every array equals the oracle's."""
     sizes = [(1 << 25) + 7, 3000, (1 << 24) + 1, 70000]
     seeds = [91, 92, 93, 94]
     arrays = [torch.arange(n, dtype=torch.int32, device=DEV) for n in sizes]
@@ -172,12 +170,4 @@ def test_large_request_in_a_batch(lanes):
     for i, n in enumerate(sizes):
         assert res[i]["status"] == 0
         assert res[i]["aux_words"] <= rp.rp_aux_bound_words(n, 0.5)
-        a = arrays[i]
-        seen = torch.zeros(n, dtype=torch.bool, device=DEV)
-        seen[a.long()] = True
-        assert bool(seen.all())
-        rng = np.random.default_rng(i)
-        pos = np.unique(np.concatenate([[0, 1, n - 2, n - 1], rng.integers(0, n, 400)]))
-        want = oracle.sample_sources(n, pos, seed=seeds[i])
-        got = a[torch.from_numpy(pos.astype(np.int64)).to(DEV)].cpu().numpy()
-        assert np.array_equal(got.astype(np.uint64), want.astype(np.uint64)), (i, n)
+        assert np.array_equal(arrays[i].cpu().numpy(), _oracle(n, seeds[i])), (i, n)
