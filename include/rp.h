@@ -48,6 +48,8 @@ extern "C" {
 #define RP_ETIMEOUT (-4) /* device watchdog fired (a barrier or the round count
                             exceeded its bound); reported through stats */
 #define RP_ECANCELED (-5) /* rp_server_destroy: the request was never launched */
+#define RP_ETOOBIG (-6) /* rp_shuffle_inplace_noalloc: the call needs more
+                           auxiliary memory than the static scratch holds */
 
 /*
  * Per-call statistics, written by the device and copied into caller memory
@@ -179,6 +181,34 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
 int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
                        const uint64_t *H, uint64_t seed, double eps, int variant,
                        void *stream, rp_stats *stats);
+
+/*
+ * rp_shuffle_inplace for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation, arguments, kernels and result, but the
+ * auxiliary words and the statistics record live in a static device array of
+ * RP_NOALLOC_SCRATCH_BYTES bytes (one per device, held until the process
+ * ends) instead of memory obtained per call.  The call allocates nothing: no
+ * hipMalloc/hipFree of any kind.  Its first call on a device looks up that
+ * device's array (and queries the device) once.
+ *   - Rejects, with RP_ETOOBIG and A untouched, a call whose plan needs more
+ *     than the array holds (256 bytes of alignment slack and the 112-byte
+ *     statistics record included).  1 MiB covers every eps at which
+ *     floor(n^(1-eps)) <= 131000 words, e.g. n = 2^30 at eps = 0.5
+ *     (256 KiB); n = 2^28 at eps = 0.25 (16 MiB) is rejected.
+ *   - Every call on a device shares that device's array and leaves its
+ *     contents behind; each call clears the words it uses before its rounds.
+ *     Calls that overlap on one device (other streams, other threads, the
+ *     same graph launched twice at once) race on the array and give wrong
+ *     results: serialise them.
+ *   - Otherwise as rp_shuffle_inplace (errors, stats, stream order; H mode
+ *     still waits for the stream after its validation pass).
+ */
+#define RP_NOALLOC_SCRATCH_BYTES (1u << 20)
+
+int rp_shuffle_inplace_noalloc(void *A, uint64_t n, uint32_t elem_bytes,
+                               const uint64_t *H, uint64_t seed, double eps,
+                               void *stream, rp_stats *stats);
 
 /*
  * The auxiliary memory that the calling thread's last rp_shuffle_inplace or

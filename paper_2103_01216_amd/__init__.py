@@ -25,10 +25,12 @@ RP_ENOMEM = -2
 RP_EDEVICE = -3
 RP_ETIMEOUT = -4
 RP_ECANCELED = -5
+RP_ETOOBIG = -6
+RP_NOALLOC_SCRATCH_BYTES = 1 << 20
 
 _ERRORS = {RP_EINVAL: "RP_EINVAL", RP_ENOMEM: "RP_ENOMEM",
            RP_EDEVICE: "RP_EDEVICE", RP_ETIMEOUT: "RP_ETIMEOUT",
-           RP_ECANCELED: "RP_ECANCELED"}
+           RP_ECANCELED: "RP_ECANCELED", RP_ETOOBIG: "RP_ETOOBIG"}
 
 STATS_FIELDS = ("k", "aux_words", "aux_bound_words", "rounds", "attempts",
                 "retries", "max_active", "self_loops", "grid",
@@ -66,6 +68,8 @@ def lib() -> ctypes.CDLL:
         L.rp_plan.argtypes = [u64, u32, ctypes.c_double, i32, ctypes.POINTER(rp_stats)]
         L.rp_shuffle_inplace.restype = i32
         L.rp_shuffle_inplace.argtypes = [vp, u64, u32, vp, u64, ctypes.c_double, vp, vp]
+        L.rp_shuffle_inplace_noalloc.restype = i32
+        L.rp_shuffle_inplace_noalloc.argtypes = [vp, u64, u32, vp, u64, ctypes.c_double, vp, vp]
         L.rp_shuffle_variant.restype = i32
         L.rp_shuffle_variant.argtypes = [vp, u64, u32, vp, u64, ctypes.c_double, i32, vp, vp]
         L.rp_seed_targets.restype = i32
@@ -163,6 +167,15 @@ def rp_shuffle_inplace(A, *, H=None, seed: int = 0, eps: float = 0.5,
     return _shuffle(A, H, seed, eps, None, stream, stats)
 
 
+def rp_shuffle_inplace_noalloc(A, *, H=None, seed: int = 0, eps: float = 0.5,
+                               stream=None, stats: bool = True):
+    """rp_shuffle_inplace through the entry point that allocates no device
+    memory (its auxiliary words live in the library's static per-device
+    scratch, RP_NOALLOC_SCRATCH_BYTES).  Raises RpError(RP_ETOOBIG) when the
+    call needs more than that.  Calls overlapping on one device race."""
+    return _shuffle(A, H, seed, eps, "noalloc", stream, stats)
+
+
 def rp_shuffle_variant(A, *, variant, H=None, seed: int = 0, eps: float = 0.5,
                        stream=None, stats: bool = True):
     """rp_shuffle_inplace under one of the reservation variants
@@ -188,16 +201,18 @@ def _shuffle(A, H, seed, eps, variant, stream, stats):
         host = torch.zeros(ctypes.sizeof(rp_stats) // 8, dtype=torch.int64,
                            pin_memory=True)
         sptr = ctypes.c_void_p(host.data_ptr())
-    if variant is None:
-        rc = lib().rp_shuffle_inplace(ctypes.c_void_p(A.data_ptr() if n else 0), n, eb,
-                                      hptr, seed & (2**64 - 1), eps,
-                                      ctypes.c_void_p(stream.cuda_stream), sptr)
+    if variant is None or variant == "noalloc":
+        fn = lib().rp_shuffle_inplace if variant is None else lib().rp_shuffle_inplace_noalloc
+        rc = fn(ctypes.c_void_p(A.data_ptr() if n else 0), n, eb,
+                hptr, seed & (2**64 - 1), eps,
+                ctypes.c_void_p(stream.cuda_stream), sptr)
     else:
         rc = lib().rp_shuffle_variant(ctypes.c_void_p(A.data_ptr() if n else 0), n, eb,
                                       hptr, seed & (2**64 - 1), eps, variant,
                                       ctypes.c_void_p(stream.cuda_stream), sptr)
     if rc != RP_OK:
-        raise RpError(rc, "rp_shuffle_inplace" if variant is None else "rp_shuffle_variant")
+        raise RpError(rc, {None: "rp_shuffle_inplace", "noalloc": "rp_shuffle_inplace_noalloc"}
+                      .get(variant, "rp_shuffle_variant"))
     return PendingStats(host, stream) if stats else None
 
 

@@ -1110,7 +1110,7 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
         // [aux words | statistics record], both inside the fixed region.
         const uint64_t aux_span = (aux_bytes + 255) / 256 * 256;
         if (aux_span + S_WORDS * 8 > cm.fixed_bytes)
-            return RP_ENOMEM;
+            return RP_ETOOBIG;
         mem = cm.fixed;
         smem = cm.fixed + aux_span;
         g_ledger.device_bytes += aux_bytes;
@@ -1209,6 +1209,71 @@ int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
                        void *stream, rp_stats *stats)
 {
     return shuffle_impl(A, n, elem_bytes, H, seed, eps, variant, stream, stats);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of the no-allocation entry point: one copy of this array per
+// device, held until the process ends.  On the host, `scratch` names a
+// host-side stand-in, never the device array: its device address is taken
+// once per device with hipGetSymbolAddress (with that device current) and
+// only that address is handed to kernels.  Every call on a device shares that
+// device's copy; it keeps the last call's contents, and rp_init_kernel clears
+// the words a call needs before its rounds start.
+__device__ __align__(256) unsigned char scratch[RP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up (and the
+// device's launch parameters queried) on the first call there.
+int scratch_of_current_device(unsigned char **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES)
+        return RP_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        DevInfo di;
+        const int rc = device_info(dev, &di);
+        if (rc != RP_OK)
+            return rc;
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return RP_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return RP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rp_shuffle_inplace_noalloc(void *A, uint64_t n, uint32_t elem_bytes,
+                               const uint64_t *H, uint64_t seed, double eps,
+                               void *stream, rp_stats *stats)
+{
+    g_ledger = AuxLedger{};
+    int rc = validate(A, n, elem_bytes, eps);
+    if (rc != RP_OK)
+        return rc;
+    if (n <= 1)
+        return shuffle_impl(A, n, elem_bytes, H, seed, eps, RP_VARIANT_FINAL, stream, stats);
+    unsigned char *base = nullptr;
+    rc = scratch_of_current_device(&base);
+    if (rc != RP_OK)
+        return rc;
+    CallMemory cm;
+    cm.fixed = base;
+    cm.fixed_bytes = RP_NOALLOC_SCRATCH_BYTES;
+    return shuffle_impl(A, n, elem_bytes, H, seed, eps, RP_VARIANT_FINAL, stream, stats, cm);
 }
 
 uint64_t rp_last_call_aux_bytes(void)
