@@ -564,6 +564,302 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
     rounds_body<M, EB, LDS>(p);
 }
 
+// ------------------------------------------------- one barrier per round
+//
+// When the auxiliary bound, not the grid, limits k (the swaps fit one per
+// lane with a few hundred per workgroup), the rounds run with one grid
+// barrier each instead of two.  Between two barriers a workgroup checks and
+// commits round r and refills and reserves round r+1.  What the second
+// barrier of rounds_body provides is obtained otherwise:
+//   * Fresh indices are handed out by quota.  At each barrier every
+//     workgroup learns the active swaps and the swaps just committed of all
+//     workgroups, and all of them derive the same quota q for the next
+//     refill: enough fresh swaps to bring the active total back to about k,
+//     never more than the fullest workgroup has free slots, never so many
+//     that a rank leaves its field.  Workgroup w then takes the fresh indices
+//     cursor-1-(w*q+j), j < q: the union over workgroups is the next
+//     contiguous range below the cursor, so the active swaps stay the top
+//     unfinished ones in sequential order, without a second exchange after
+//     the commits.  A workgroup has WG1 lanes for about PER_WG1 active swaps,
+//     so the quota always finds free slots.
+//   * Records are read after the barrier, together with the check loads:
+//     the barrier follows every commit of the previous round.  The targets
+//     of the next fresh indices are computed (into LDS) while those loads are
+//     in flight.
+//   * A fast workgroup's reservations of round r+1 may land while a slow one
+//     still checks round r.  They carry a larger round tag, so they can only
+//     make such a check lose, never win wrongly.  The top active swap (whose
+//     rank every workgroup learns at the barrier) commits regardless: nothing
+//     active precedes it, so it always may, and every round makes progress.
+//   * The dense window has three parities.  Round r+1 sets parity (r+1) mod 3
+//     and clears parity (r+2) mod 3, whose last readers (the checks of round
+//     r-1) finished before the barrier that opened round r.
+constexpr int WG1 = 512;                // lanes of a one-barrier workgroup
+constexpr int WAVES1 = WG1 / 64;
+constexpr uint32_t PER_WG1 = 256;       // active swaps per workgroup the grid is sized for
+constexpr uint32_t WPAR1 = 3;           // window parities
+constexpr double WFRAC1 = 2.0;          // window keys per active swap
+
+template <int EB>
+__global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
+{
+    __shared__ uint32_t sh_scan[WAVES1];
+    __shared__ uint32_t sh_pay[WAVES1];
+    __shared__ uint32_t sh_age[WAVES1];
+    __shared__ uint32_t sh_h[WG1];
+    __shared__ uint64_t sh_res[6];
+
+    const uint32_t G = p.wg_count, w = blockIdx.x - p.wg_first, t = threadIdx.x;
+    const uint32_t wave = t >> 6, lane = t & 63;
+    const uint32_t W = p.bmw * 32u;
+    uint32_t *const slots = p.slots;
+    uint32_t *const bm = p.bm;
+    using R = Rec<EB == 0 ? 4 : EB>;
+
+    uint32_t epoch = 0;
+    uint32_t src = EMPTY, tgt = 0;
+    uint32_t cursor = p.n;        // rank base of the round last reserved
+    uint64_t rr = 0;              // rounds reserved so far
+    uint64_t attempts = 0, retries = 0, selfl = 0, maxact = 0, throttled = 0;
+    bool failed = false;
+    uint32_t q = (uint32_t)min<uint64_t>(((uint64_t)p.k + G - 1) / G, (uint64_t)WG1);
+    uint32_t take = (uint32_t)min<uint64_t>((uint64_t)G * q, p.n);
+    uint32_t top = EMPTY;         // rank of the top active swap of the round to check
+    uint64_t prevA = 0;           // active swaps of the round checked last
+    const double rG = 1.0 / (double)G;
+
+    for (;;) {
+        // ---- check round rr-1: issue the loads the decision needs
+        const bool act = src != EMPTY;
+        const uint32_t ds = src - cursor;
+        uint32_t t1 = 0, q1 = 0;
+        if (act) {
+            const uint32_t par = (uint32_t)((rr - 1) % WPAR1);
+            t1 = ld(&slots[slot1(tgt, p.T)]);
+            q1 = ds < W ? ld(&bm[(uint64_t)par * p.bmw + (ds >> 5)])
+                        : ld(&slots[slot1(src, p.T)]);
+        }
+        // ---- meanwhile: targets of this workgroup's fresh indices
+        const uint32_t base_w = w * q;
+        if (t < q && base_w + t < take)
+            sh_h[t] = target_of(p, cursor - 1u - (base_w + t));
+        // ---- decide (the records are not needed for it; winners move them
+        // while the refill and the reservations proceed)
+        uint32_t won = 0;
+        const uint32_t ws = src, wt = tgt;
+        if (act) {
+            const uint32_t tag = (uint32_t)((rr - 1) % TAG_CYCLE);
+            const uint32_t v = (tag << RANKB) | ds;
+            // Target: still the maximum in the slot of H[s].  Source: no
+            // active swap targets s (window bit, or the slot of key s).
+            bool win = t1 == v;
+            if (ds < W)
+                win = win && !((q1 >> (ds & 31u)) & 1u);
+            else
+                win = win && q1 <= v;
+            win = win || ds == top;
+            attempts++;
+            if (win) {
+                src = EMPTY;
+                won = 1;
+            } else {
+                retries++;
+            }
+        }
+        // Winners read both records now (the barrier followed every commit
+        // of the previous round, and no other winner of this round touches
+        // them); they are written back swapped after the reservations.
+        R r_s, r_h;
+        if constexpr (EB != 0) {
+            if (won) {
+                r_s.load(p.A, ws);
+                r_h.load(p.A, wt);
+            }
+        }
+        // ---- refill: the free slots take the fresh indices in order
+        const bool f = src == EMPTY;
+        const uint64_t fb = __ballot(f);
+        if (lane == 0)
+            sh_scan[wave] = (uint32_t)__popcll(fb);
+        __syncthreads();
+        uint32_t below = 0;
+#pragma unroll
+        for (int i = 0; i < WAVES1; i++)
+            below += ((uint32_t)i < wave) ? sh_scan[i] : 0u;
+        const uint32_t j = below + lane_rank(fb);
+        if (f && j < q && base_w + j < take) {
+            const uint32_t s = cursor - 1u - (base_w + j);
+            const uint32_t h = sh_h[j];
+            if (h == s) {
+                selfl++;
+            } else {
+                src = s;
+                tgt = h;
+            }
+        }
+        cursor -= take;
+        const uint32_t tag = (uint32_t)(rr % TAG_CYCLE);
+
+        // Every TAG_CYCLE rounds the reservation array is reset between two
+        // extra barriers: the first lets every workgroup finish its checks
+        // of the old tags, the second every clear before a reservation with
+        // the new ones.
+        if (tag == 0 && rr > 0) {
+            if (!plain_barrier(p, ++epoch, sh_res)) {
+                failed = true;
+                break;
+            }
+            for (uint32_t i = w * WG1 + t; i < p.T; i += G * WG1)
+                clear_rmw(&slots[i]);
+            if (!plain_barrier(p, ++epoch, sh_res)) {
+                failed = true;
+                break;
+            }
+        }
+        // ---- reserve round rr
+        {
+            const uint32_t cp = (uint32_t)((rr + 1) % WPAR1);
+            for (uint32_t i = w * WG1 + t; i < p.bmw; i += G * WG1)
+                clear_rmw(&bm[(uint64_t)cp * p.bmw + i]);
+        }
+        if (src != EMPTY) {
+            const uint32_t v = (tag << RANKB) | (src - cursor);
+            __hip_atomic_fetch_max(&slots[slot1(tgt, p.T)], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t d = tgt - cursor;
+            if (tgt >= cursor && d < W)
+                __hip_atomic_fetch_or(&bm[(uint64_t)(rr % WPAR1) * p.bmw + (d >> 5)],
+                                      1u << (d & 31u), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+        }
+        rr++;
+        // ---- winners of the round just checked exchange their records
+        if (won) {
+            if constexpr (EB != 0) {
+                r_h.store(p.A, ws);
+                r_s.store(p.A, wt);
+            } else {
+                swap_generic(p.A, p.eb, ws, wt);
+            }
+        }
+
+        // ---- barrier: active swaps, swaps just committed, oldest rank
+        const bool a = src != EMPTY;
+        const uint32_t xw = ((uint32_t)__popcll(__ballot(a)) << 16) |
+                            (uint32_t)__popcll(__ballot(won != 0));
+        const uint32_t agew = wave_max(a ? src - cursor : 0u);
+        if (lane == 0)
+            sh_pay[wave] = xw;
+        if (lane == 0)
+            sh_age[wave] = agew;
+        wait_mem();
+        __syncthreads();
+        ++epoch;
+        if (wave == 0) {
+            uint32_t wgx = 0, wgage = 0;
+#pragma unroll
+            for (int i = 0; i < WAVES1; i++) {
+                wgx += sh_pay[i];
+                wgage = max(wgage, sh_age[i]);
+            }
+            uint64_t totA = 0, totW = 0;
+            uint32_t maxA = 0, agemax = 0;
+            bool ok = true;
+            const uint64_t pay = ((uint64_t)(wgx >> 16) << 34) |
+                                 ((uint64_t)(wgx & 0xFFFFu) << 24) | wgage;
+            if (G == 1) {
+                totA = maxA = wgx >> 16;
+                totW = wgx & 0xFFFFu;
+                agemax = wgage;
+            } else {
+                ok = gather_wave0(p, epoch, pay, [&](uint32_t, uint64_t y) {
+                    const uint32_t av = (uint32_t)(y >> 34) & 0x3FFFu;
+                    totA += av;
+                    totW += (uint32_t)(y >> 24) & 0x3FFu;
+                    maxA = max(maxA, av);
+                    agemax = max(agemax, (uint32_t)y & RANKMAX);
+                });
+                totA = wave_sum64(totA);
+                totW = wave_sum64(totW);
+                maxA = wave_max(maxA);
+                agemax = wave_max(agemax);
+            }
+            if (lane == 0) {
+                sh_res[0] = totA;
+                sh_res[1] = totW;
+                sh_res[2] = maxA;
+                sh_res[3] = ok ? 0u : 1u;
+                sh_res[4] = agemax;
+            }
+        }
+        __syncthreads();
+        if (sh_res[3]) {
+            failed = true;
+            break;
+        }
+        const uint64_t totA = sh_res[0], totW = sh_res[1];
+        const uint32_t maxA = (uint32_t)sh_res[2], agemax = (uint32_t)sh_res[4];
+        maxact = max(maxact, totA);
+        if (cursor == 0 && totA == 0)
+            break;
+        if (rr > p.max_rounds) {
+            if (t == 0)
+                st(p.err, 2u);
+            failed = true;
+            break;
+        }
+        // ---- quota of the next refill (the same in every workgroup): the
+        // active swaps that will remain after the coming check are estimated
+        // from the last check's win rate, and the quota refills them to k.
+        // (All counts are below 2^32; the quotients are taken in double
+        // precision, which every workgroup evaluates identically and which
+        // is exact for these magnitudes.)
+        top = totA ? agemax : EMPTY;
+        const uint32_t a32 = (uint32_t)totA;
+        const uint32_t expect_w =
+            prevA ? (uint32_t)((double)totA * (double)totW / (double)prevA) : a32 / 2u;
+        prevA = totA;
+        const uint32_t want = p.k + expect_w > a32 ? p.k + expect_w - a32 : 0u;
+        uint32_t qq = min((uint32_t)std::ceil((double)want * rG), (uint32_t)WG1 - maxA);
+        const uint32_t room =
+            agemax < p.rank_cap ? (uint32_t)((double)(p.rank_cap - agemax) * rG) : 0u;
+        if (qq > room) {
+            qq = room;
+            throttled++;
+        }
+        if (qq == 0 && totA == 0 && cursor > 0)
+            qq = 1;
+        q = qq;
+        take = (uint32_t)min<uint64_t>((uint64_t)G * q, cursor);
+    }
+
+    // ---- statistics
+    const uint64_t s_att = wave_sum64(attempts), s_ret = wave_sum64(retries),
+                   s_self = wave_sum64(selfl);
+    if (lane == 0) {
+        __hip_atomic_fetch_add(&p.dstats[S_ATTEMPTS], s_att, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&p.dstats[S_RETRIES], s_ret, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&p.dstats[S_SELF], s_self, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (t == 0) {
+        if (w == 0) {
+            st(&p.dstats[S_ROUNDS], rr > 0 ? rr - 1 : 0);
+            st(&p.dstats[S_MAXACT], maxact);
+            st(&p.dstats[S_THROTTLED], throttled);
+            // The quota aims at k active swaps; a round may hold a few more
+            // (the winners of the round being refilled are not known yet),
+            // so the register-held state is counted from the largest round.
+            constexpr uint64_t per_swap = 8 + (EB == 0 ? 0 : 2 * EB);
+            st(&p.dstats[S_INFLIGHT], (std::max<uint64_t>(maxact, p.k) * per_swap + 7) / 8);
+        }
+        if (failed)
+            st(&p.dstats[S_STATUS], (uint64_t)(int64_t)RP_ETIMEOUT);
+    }
+}
+
 // Several independent shuffles in one cooperative launch: shuffle i runs on
 // workgroups [g[i].wg_first, g[i].wg_first + g[i].wg_count) with its own
 // auxiliary words, its rounds synchronised among those workgroups only.
@@ -654,9 +950,12 @@ __global__ void rp_seed_targets_kernel(const uint64_t *idx, uint64_t count,
 struct Plan {
     bool single;      // k = 1 path
     bool lds;         // one workgroup: slots and window in dynamic LDS
+    bool onebar;      // one barrier per round (rp_rounds1_kernel, WG1 lanes)
     uint32_t G, M, k, T, bmw;
+    uint32_t wpar;    // window parities: 2, or 3 with one barrier per round
     uint64_t bound, aux_bytes;
     int eb_class;     // 4, 8, 16 or 0
+    int eb1;          // record size the one-barrier kernel holds: 4, 8, 16, 64 or 0
 };
 
 double table_ratio()
@@ -713,13 +1012,74 @@ int choose_linear_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_
     return RP_OK;
 }
 
+// Device bytes of the one-barrier path for a target of k active swaps on G
+// workgroups (0: the default grid for k): the slot array, three window
+// parities, the gather flags of the grid and the error word.
+uint64_t aux_bytes_for1(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_out,
+                        uint64_t *G_out)
+{
+    if (G == 0)
+        G = (k + PER_WG1 - 1) / PER_WG1;
+    const uint64_t T = std::max<uint64_t>(2, (uint64_t)std::ceil(table_ratio() * (double)k));
+    const uint64_t bmw = std::max<uint64_t>(1, (uint64_t)std::ceil(WFRAC1 * (double)k / 32.0));
+    if (T_out) *T_out = T;
+    if (bmw_out) *bmw_out = bmw;
+    if (G_out) *G_out = G;
+    // slot array and window padded to 8 bytes: the gather flags after them
+    // are 64-bit words
+    return ((T * 4 + 7) / 8) * 8 + ((WPAR1 * bmw * 4 + 7) / 8) * 8 + 8 + (G > 1 ? 2 * G * 8 : 0);
+}
+
+// The one-barrier plan, when it applies: the bound (not the grid) limits
+// the active swaps, they need at least two workgroups of WG1 lanes and at
+// most `wg_cap` of them, and no other launch shape was asked for.
+bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t wg_cap, Plan *pl)
+{
+    if (env_int("RP_ONEBAR", 1) == 0)
+        return false;
+    const int want_m = env_int("RP_SLOTS", 0), want_g = env_int("RP_GRID", 0);
+    if (want_m > 1)
+        return false;
+    // A fixed grid (RP_GRID) is counted with its own gather flags.
+    const uint64_t G_fixed = want_g > 0 ? (uint64_t)want_g : 0;
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (aux_bytes_for1(mid, G_fixed, nullptr, nullptr, nullptr) <= budget) lo = mid;
+        else hi = mid - 1;
+    }
+    uint64_t T, bmw, G;
+    const uint64_t k = lo;
+    const uint64_t aux = aux_bytes_for1(k, G_fixed, &T, &bmw, &G);
+    // every workgroup must keep room for its quota
+    if (G_fixed > 0 && G_fixed * WG1 < 2 * k)
+        return false;
+    if (G < 2 || G > std::min<uint64_t>(MAXG, wg_cap))
+        return false;
+    pl->onebar = true;
+    pl->wpar = WPAR1;
+    pl->k = (uint32_t)k;
+    pl->G = (uint32_t)G;
+    pl->M = 1;
+    pl->T = (uint32_t)T;
+    pl->bmw = (uint32_t)bmw;
+    pl->aux_bytes = aux;
+    pl->eb1 = (eb == 4 || eb == 8 || eb == 16 || eb == 64) ? (int)eb : 0;
+    return true;
+}
+
+// occ1: workgroups of the one-barrier kernel a compute unit holds, or 0 when
+// that path may not be used (group launches, variants).
 int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
-                Plan *pl)
+                Plan *pl, int occ1 = 0)
 {
     std::memset(pl, 0, sizeof(*pl));
     pl->bound = rp_aux_bound_words(n, eps);
     pl->eb_class = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
+    pl->wpar = 2;
     const uint64_t budget = pl->bound * 8;
+    if (occ1 > 0 && choose_plan1(n, eb, budget, (uint64_t)cus * occ1, pl))
+        return RP_OK;
     // The persistent path needs k >= 2.
     if (aux_bytes_for(2, 1, nullptr, nullptr) > budget) {
         pl->single = true;
@@ -868,7 +1228,24 @@ struct DevInfo {
     bool ok = false;
     int cus = 256;
     int occ[4][5] = {};  // [M index][eb class index] co-resident WGs per CU
+    int occ1[5] = {};    // one-barrier kernel, by eb1 index
 };
+
+using KernelFn1 = void (*)(Params);
+
+KernelFn1 pick_kernel1(int eb1)
+{
+    switch (eb1) {
+    case 4: return rp_rounds1_kernel<4>;
+    case 8: return rp_rounds1_kernel<8>;
+    case 16: return rp_rounds1_kernel<16>;
+    case 64: return rp_rounds1_kernel<64>;
+    default: return rp_rounds1_kernel<0>;
+    }
+}
+
+int eb1_index(int eb1) { return eb1 == 4 ? 0 : eb1 == 8 ? 1 : eb1 == 16 ? 2 : eb1 == 64 ? 3 : 4; }
+int eb1_of(uint32_t eb) { return (eb == 4 || eb == 8 || eb == 16 || eb == 64) ? (int)eb : 0; }
 
 std::mutex g_mu;
 std::vector<DevInfo> g_dev;
@@ -896,6 +1273,15 @@ int device_info(int dev, DevInfo *out)
                     return RP_EDEVICE;
                 d.occ[a][b] = std::max(occ, 1);
             }
+        const int eb1s[5] = {4, 8, 16, 64, 0};
+        for (int b = 0; b < 5; b++) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ, reinterpret_cast<const void *>(pick_kernel1(eb1s[b])), WG1, 0) !=
+                hipSuccess)
+                return RP_EDEVICE;
+            d.occ1[b] = occ;
+        }
         d.ok = true;
     }
     *out = d;
@@ -914,7 +1300,7 @@ void fill_host_stats(const Plan &pl, rp_stats *s)
 {
     std::memset(s, 0, sizeof(*s));
     s->k = pl.k;
-    s->inflight_words = inflight_words_for(pl.k, pl.single ? 0 : pl.eb_class);
+    s->inflight_words = inflight_words_for(pl.k, pl.single ? 0 : pl.onebar ? pl.eb1 : pl.eb_class);
     s->aux_words = (pl.aux_bytes + 7) / 8;
     s->aux_bound_words = pl.bound;
     s->grid = pl.G;
@@ -948,7 +1334,7 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
     if (rc != RP_OK)
         return rc;
     int occ[4];
-    int cus = 256;
+    int cus = 256, occ1 = 1;
     const int ebc = (elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16) ? (int)elem_bytes : 0;
     if (device >= 0) {
         DevInfo d;
@@ -958,12 +1344,13 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
         cus = d.cus;
         for (int a = 0; a < 4; a++)
             occ[a] = d.occ[a][eb_index(ebc)];
+        occ1 = d.occ1[eb1_index(eb1_of(elem_bytes))];
     } else {
         for (int a = 0; a < 4; a++)
             occ[a] = 2;
     }
     Plan pl;
-    rc = choose_plan(n, elem_bytes, eps, cus, occ, &pl);
+    rc = choose_plan(n, elem_bytes, eps, cus, occ, &pl, occ1);
     if (rc != RP_OK)
         return rc;
     if (stats_out)
@@ -972,6 +1359,34 @@ int rp_plan(uint64_t n, uint32_t elem_bytes, double eps, int device,
 }
 
 }  // extern "C"
+
+namespace rpint {
+
+// The workgroups rp_shuffle_group gives a shuffle of these arguments, for
+// packing group launches (0 when it would not be part of a group: k = 1, or
+// more than one slot per lane).
+int group_grid(uint64_t n, uint32_t elem_bytes, double eps, int device, uint64_t *grid)
+{
+    int rc = validate(reinterpret_cast<void *>(uintptr_t{256}), n, elem_bytes, eps);
+    if (rc != RP_OK)
+        return rc;
+    DevInfo d;
+    rc = device_info(device, &d);
+    if (rc != RP_OK)
+        return rc;
+    const int ebc = (elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16) ? (int)elem_bytes : 0;
+    int occ[4];
+    for (int a = 0; a < 4; a++)
+        occ[a] = d.occ[a][eb_index(ebc)];
+    Plan pl;
+    rc = choose_plan(n, elem_bytes, eps, d.cus, occ, &pl);
+    if (rc != RP_OK)
+        return rc;
+    *grid = (pl.single || pl.M != 1) ? 0 : pl.G;
+    return RP_OK;
+}
+
+}  // namespace rpint
 
 namespace {
 
@@ -1022,7 +1437,7 @@ void setup_params(Params &p, const Plan &pl, int variant, bool lds_tab, void *A,
             p.slots = reinterpret_cast<uint32_t *>(cur);
             cur += ((uint64_t)pl.T * 4 + 7) / 8 * 8;
             p.bm = reinterpret_cast<uint32_t *>(cur);
-            cur += 2ull * pl.bmw * 4;
+            cur += ((uint64_t)pl.wpar * pl.bmw * 4 + 7) / 8 * 8;
         }
         if (pl.G > 1) {
             p.flags = reinterpret_cast<uint64_t *>(cur);
@@ -1094,8 +1509,9 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     for (int a = 0; a < 4; a++)
         occ[a] = di.occ[a][eb_index(ebc)];
     Plan pl;
+    const int occ1 = variant == RP_VARIANT_FINAL ? di.occ1[eb1_index(eb1_of(elem_bytes))] : 0;
     rc = variant == RP_VARIANT_LINEAR ? choose_linear_plan(n, elem_bytes, eps, di.cus, occ, &pl)
-                                      : choose_plan(n, elem_bytes, eps, di.cus, occ, &pl);
+                                      : choose_plan(n, elem_bytes, eps, di.cus, occ, &pl, occ1);
     if (rc != RP_OK)
         return rc;
 
@@ -1146,6 +1562,11 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
 
     Params p{};
     setup_params(p, pl, variant, lds_tab, A, n, elem_bytes, H, seed, base, dstats);
+    // The gather flags are 64-bit atomics and must be naturally aligned.
+    if ((reinterpret_cast<uintptr_t>(p.flags) & 7u) != 0) {
+        (void)release();
+        return RP_EDEVICE;
+    }
 
     if (H != nullptr) {
         // H mode: reject H[i] > i before anything moves.
@@ -1166,6 +1587,14 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     if (pl.single) {
         rp_single_kernel<<<1, 64, 0, stream>>>(p);
         if (hipGetLastError() != hipSuccess) {
+            (void)release();
+            return RP_EDEVICE;
+        }
+    } else if (pl.onebar) {
+        void *args[] = {&p};
+        if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pick_kernel1(pl.eb1)),
+                                       dim3(pl.G), dim3(WG1), args, 0, stream) != hipSuccess) {
+            (void)hipGetLastError();
             (void)release();
             return RP_EDEVICE;
         }

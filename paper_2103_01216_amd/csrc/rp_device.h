@@ -179,6 +179,25 @@ template <> struct Rec<16> {
     }
 };
 
+template <> struct Rec<64> {
+    static constexpr int LOADS = 8;
+    uint64_t w[8];
+    __device__ void load(const unsigned char *A, uint32_t i)
+    {
+        const uint64_t *q = reinterpret_cast<const uint64_t *>(A) + 8ull * i;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            w[u] = ld(q + u);
+    }
+    __device__ void store(unsigned char *A, uint32_t i) const
+    {
+        uint64_t *q = reinterpret_cast<uint64_t *>(A) + 8ull * i;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            st(q + u, w[u]);
+    }
+};
+
 // Swap two records of eb bytes (multiple of 4) word by word.
 __device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
                                              uint32_t a, uint32_t b)
@@ -205,6 +224,13 @@ __device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
             st(pb + j, x);
         }
     }
+}
+
+// Number of lanes below this one whose bit is set in the wave mask m.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)

@@ -34,6 +34,11 @@
 #include "rp.h"
 #include "rp_arena.h"
 
+namespace rpint {
+// rp.hip: workgroups rp_shuffle_group gives one shuffle (0: not groupable).
+int group_grid(uint64_t n, uint32_t elem_bytes, double eps, int device, uint64_t *grid);
+}
+
 namespace {
 
 constexpr int N_SMALL_STREAMS = 2;
@@ -463,11 +468,10 @@ int launch_alone(Server &s, int si)
             const rp_server_request &q = s.reqs[tk].q;
             if (q.elem_bytes != eb)
                 continue;
-            rp_stats ps{};
             uint64_t g = cap;   // unknown or more than one slot per lane: alone
-            if (rp_plan(q.n, q.elem_bytes, q.eps, s.device, &ps) == RP_OK && ps.grid &&
-                ps.slots_per_lane == 1)
-                g = ps.grid;
+            uint64_t gg = 0;
+            if (rpint::group_grid(q.n, q.elem_bytes, q.eps, s.device, &gg) == RP_OK && gg)
+                g = gg;
             if (lim > 0 && (grid + g > cap || lim == GROUP_MAX))
                 break;
             grid += g;

@@ -23,5 +23,10 @@ def shuffled_identity(n: int, seed: int) -> np.ndarray:
 
 def device_copy(n: int, seed: int, device):
     """shuffled_identity(n, seed) as a device int64 tensor."""
+    import warnings
     import torch
-    return torch.from_numpy(shuffled_identity(n, seed)).to(device)
+    with warnings.catch_warnings():
+        # the cached array is read-only on purpose; the tensor only feeds a copy
+        warnings.simplefilter("ignore", UserWarning)
+        host = torch.from_numpy(shuffled_identity(n, seed))
+    return host.to(device)

@@ -3,8 +3,8 @@ each on its own group of workgroups.
 
 Every request's output must be its own Knuth shuffle (the oracle), the same
 bytes as a call of its own, with the plan (k, auxiliary words) a call of its
-own would get; a bad request rejects the whole group with every array
-untouched.
+own on the same two-barrier rounds kernel would get; a bad request rejects the
+whole group with every array untouched.
 """
 import numpy as np
 import pytest
@@ -25,7 +25,7 @@ def _want(n, seed):
 
 
 @pytest.mark.parametrize("eps", [0.5, 0.65, 0.4])
-def test_group_equals_oracle(eps):
+def test_group_equals_oracle(eps, monkeypatch):
     sizes = [(1 << 20) + 7, 1000, (1 << 18) + 3, 50_000, 2, 1]
     seeds = [11 * i + 3 for i in range(len(sizes))]
     arrays = [workloads.identity(n, torch.int64, DEV) for n in sizes]
@@ -35,16 +35,22 @@ def test_group_equals_oracle(eps):
         assert st["aux_words"] <= st["aux_bound_words"] == rp.rp_aux_bound_words(n, eps)
         assert np.array_equal(A.cpu().numpy(), _want(n, sd)), (n, eps)
         if n > 1:
+            # group launches run every shuffle on the two-barrier rounds
+            # kernel, planned as a call of its own on that kernel would be
+            monkeypatch.setenv("RP_ONEBAR", "0")
             alone = rp.rp_plan(n, 8, eps, device=0)
+            monkeypatch.delenv("RP_ONEBAR")
             assert st["k"] == alone["k"] and st["aux_words"] == alone["aux_words"]
 
 
-def test_group_equals_calls_of_their_own():
+def test_group_equals_calls_of_their_own(monkeypatch):
     sizes = [(1 << 24) + 5, 1 << 22, (1 << 23) + 1, 3 << 20]
     seeds = [5, 6, 7, 8]
     grouped = [workloads.identity(n, torch.int64, DEV) for n in sizes]
     alone = [workloads.identity(n, torch.int64, DEV) for n in sizes]
     stats = rp.rp_shuffle_group(grouped, seeds=seeds, eps=0.5)
+    # the same kernel alone: identical rounds and attempts, not just bytes
+    monkeypatch.setenv("RP_ONEBAR", "0")
     for A, B, sd, st in zip(grouped, alone, seeds, stats):
         s = rp.rp_shuffle_inplace(B, seed=sd, eps=0.5).get()
         assert st["status"] == 0 and s["status"] == 0

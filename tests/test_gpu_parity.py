@@ -31,8 +31,9 @@ def _check_stats(s, n, H_np=None):
         nonself = n - selfl
         assert s["self_loops"] == selfl
         assert s["attempts"] == nonself + s["retries"]
-        if s["k"] > 0:
-            assert s["rounds"] >= -(-nonself // s["k"])
+        # each round attempts at most max_active swaps
+        if s["max_active"] > 0:
+            assert s["rounds"] >= -(-nonself // s["max_active"])
         # Each round either commits a swap (the top active one always wins)
         # or only retires self-loops while consuming k fresh indices.
         assert s["rounds"] <= nonself + -(-n // max(1, s["k"])) + 2
@@ -291,8 +292,12 @@ def test_rank_throttle_engages_under_full_parity(monkeypatch):
 
 
 def test_inflight_words_reported():
+    """Register-held state: source, target and both records per active
+    swap, counted over the largest round (at least k)."""
     n = 1 << 20
     for dtype, eb in ((torch.int32, 4), (torch.int64, 8)):
         A = workloads.identity(n, dtype, DEV)
         s = _run(A, seed=2, eps=0.5)
-        assert s["inflight_words"] == -(-s["k"] * (8 + 2 * eb) // 8)
+        held = max(s["max_active"], s["k"])
+        assert s["inflight_words"] == -(-held * (8 + 2 * eb) // 8)
+        assert s["max_active"] <= s["k"] * 11 // 10
