@@ -51,13 +51,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
-KERNEL_NAME = "rp_rounds_kernel"
+KERNEL_NAME = "rp_rounds1_kernel"
 WORKLOAD = {"n": 1 << 30, "elem_bytes": 8, "eps": 0.5, "seed": 1}
 BATCH = {"count": 4096, "lo_log2": 8, "hi_log2": 20, "size_seed": 12345,
          "seed_base": 1000, "eps": 0.5}
 CSRC = os.path.join(ROOT, "paper_2103_01216_amd", "csrc")
 TRAFFIC = {
-    "plain": (os.path.join(ROOT, "profiles", "rp_rounds_kernel_n2p30_int64_eps0.5_traffic.json"),
+    "plain": (os.path.join(ROOT, "profiles", "rp_rounds1_kernel_n2p30_int64_eps0.5_traffic.json"),
               [os.path.join(CSRC, f) for f in ("rp.hip", "rp_device.h")]),
     "batch": (os.path.join(ROOT, "profiles", "rp_batch_kernel_4096_loguniform_int32_traffic.json"),
               [os.path.join(CSRC, f) for f in ("rp_batch.hip", "rp_device.h")]),

@@ -596,9 +596,11 @@ __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 //     r-1) finished before the barrier that opened round r.
 constexpr int WG1 = 512;                // lanes of a one-barrier workgroup
 constexpr int WAVES1 = WG1 / 64;
-constexpr uint32_t PER_WG1 = 256;       // active swaps per workgroup the grid is sized for
+constexpr uint32_t PER_WG1 = 256;       // most active swaps per workgroup the grid is sized for
+constexpr uint32_t MIN_PER_WG1 = 64;    // fewest, when the grid is widened
+constexpr uint32_t WIDE_NUM = 11, WIDE_DEN = 16;  // widened grid: 11/16 of the compute units
 constexpr uint32_t WPAR1 = 3;           // window parities
-constexpr double WFRAC1 = 2.0;          // window keys per active swap
+constexpr double WFRAC1 = 1.5;          // window keys per active swap
 
 template <int EB>
 __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
@@ -1013,15 +1015,46 @@ int choose_linear_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_
 }
 
 // Device bytes of the one-barrier path for a target of k active swaps on G
-// workgroups (0: the default grid for k): the slot array, three window
-// parities, the gather flags of the grid and the error word.
-uint64_t aux_bytes_for1(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_out,
-                        uint64_t *G_out)
+// workgroups (0: the default grid for k on `cus` compute units): the slot
+// array, three window parities, the gather flags of the grid and the error
+// word.
+// Tuning overrides of the one-barrier plan (environment; defaults are the
+// measured best): RP_WINDOW window keys per active swap, RP_PER_WG active
+// swaps per workgroup (fixes the grid at k / RP_PER_WG).
+double window_frac1()
+{
+    const char *v = getenv("RP_WINDOW");
+    const double r = (v && *v) ? atof(v) : WFRAC1;
+    return (r >= 0.25 && r <= 8.0) ? r : WFRAC1;
+}
+
+// The grid for k active swaps on `cus` compute units: PER_WG1 swaps per
+// workgroup, unless that leaves most of the chip idle; then the grid widens
+// to WIDE_NUM/WIDE_DEN of the compute units (at least MIN_PER_WG1 swaps per
+// workgroup).  A round's memory operations are issued lane by lane, so a
+// round is shorter when its swaps are spread over more compute units; the
+// flag barrier grows with the grid, which is why it is not widened further
+// (measured: n = 2^28 int64 at eps 0.5, 107 / 169 / 210 workgroups ->
+// 101.6 / 100.0 / 104.9 ms; 2^26 records of 64 B, 54 / 105 / 205 ->
+// 114.5 / 81.9 / 69.3 ms).
+uint64_t grid1_for(uint64_t k, uint64_t cus)
+{
+    const int v = env_int("RP_PER_WG", 0);
+    if (v >= 16 && v <= WG1 / 2)
+        return (k + (uint64_t)v - 1) / (uint64_t)v;
+    const uint64_t g_full = (k + PER_WG1 - 1) / PER_WG1;
+    const uint64_t g_wide = std::min<uint64_t>((k + MIN_PER_WG1 - 1) / MIN_PER_WG1,
+                                               cus * WIDE_NUM / WIDE_DEN);
+    return std::max(g_full, g_wide);
+}
+
+uint64_t aux_bytes_for1(uint64_t k, uint64_t G, uint64_t cus, uint64_t *T_out,
+                        uint64_t *bmw_out, uint64_t *G_out)
 {
     if (G == 0)
-        G = (k + PER_WG1 - 1) / PER_WG1;
+        G = grid1_for(k, cus);
     const uint64_t T = std::max<uint64_t>(2, (uint64_t)std::ceil(table_ratio() * (double)k));
-    const uint64_t bmw = std::max<uint64_t>(1, (uint64_t)std::ceil(WFRAC1 * (double)k / 32.0));
+    const uint64_t bmw = std::max<uint64_t>(1, (uint64_t)std::ceil(window_frac1() * (double)k / 32.0));
     if (T_out) *T_out = T;
     if (bmw_out) *bmw_out = bmw;
     if (G_out) *G_out = G;
@@ -1033,7 +1066,8 @@ uint64_t aux_bytes_for1(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_o
 // The one-barrier plan, when it applies: the bound (not the grid) limits
 // the active swaps, they need at least two workgroups of WG1 lanes and at
 // most `wg_cap` of them, and no other launch shape was asked for.
-bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t wg_cap, Plan *pl)
+bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t cus, uint64_t wg_cap,
+                  Plan *pl)
 {
     if (env_int("RP_ONEBAR", 1) == 0)
         return false;
@@ -1045,12 +1079,12 @@ bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t wg_cap, Pla
     uint64_t lo = 0, hi = n;
     while (lo < hi) {
         const uint64_t mid = (lo + hi + 1) / 2;
-        if (aux_bytes_for1(mid, G_fixed, nullptr, nullptr, nullptr) <= budget) lo = mid;
+        if (aux_bytes_for1(mid, G_fixed, cus, nullptr, nullptr, nullptr) <= budget) lo = mid;
         else hi = mid - 1;
     }
     uint64_t T, bmw, G;
     const uint64_t k = lo;
-    const uint64_t aux = aux_bytes_for1(k, G_fixed, &T, &bmw, &G);
+    const uint64_t aux = aux_bytes_for1(k, G_fixed, cus, &T, &bmw, &G);
     // every workgroup must keep room for its quota
     if (G_fixed > 0 && G_fixed * WG1 < 2 * k)
         return false;
@@ -1078,7 +1112,7 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
     pl->eb_class = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
     pl->wpar = 2;
     const uint64_t budget = pl->bound * 8;
-    if (occ1 > 0 && choose_plan1(n, eb, budget, (uint64_t)cus * occ1, pl))
+    if (occ1 > 0 && choose_plan1(n, eb, budget, (uint64_t)cus, (uint64_t)cus * occ1, pl))
         return RP_OK;
     // The persistent path needs k >= 2.
     if (aux_bytes_for(2, 1, nullptr, nullptr) > budget) {

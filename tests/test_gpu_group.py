@@ -120,9 +120,11 @@ def test_group_of_sixteen_within_capacity():
         assert st["status"] == 0 and np.array_equal(A.cpu().numpy(), _want(n, sd))
 
 
-def test_group_beyond_capacity_is_refused():
+def test_group_beyond_capacity_is_refused(monkeypatch):
     cap = rp.rp_group_capacity(8)
     n, eps = 1 << 22, 0.35
+    # the grid a group gives the shuffle: its two-barrier plan
+    monkeypatch.setenv("RP_ONEBAR", "0")
     g = rp.rp_plan(n, 8, eps, device=0)["grid"]
     count = -(-(cap + 1) // g)
     if count > 16:
