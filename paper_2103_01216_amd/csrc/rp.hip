@@ -350,7 +350,7 @@ __device__ __forceinline__ void rounds_body(const Params &p)
         // Every TAG_CYCLE rounds: reset the reservation array behind an
         // extra barrier, so that tags restart from 0 over an empty array.
         if (tag == 0 && rounds > 0 && !linear) {
-            for (uint32_t i = w * WG + t; i < p.T; i += G * WG)
+            for (uint32_t i = w + G * t; i < p.T; i += G * WG)
                 clear_rmw(&slots[i]);
             if (!plain_barrier(p, ++epoch, sh_res)) {
                 failed = true;
@@ -380,7 +380,7 @@ __device__ __forceinline__ void rounds_body(const Params &p)
         // the slot(s) of H[s]; dense window bit
         {
             const uint32_t op = par ^ 1u;
-            for (uint32_t i = w * WG + t; i < p.bmw; i += G * WG)
+            for (uint32_t i = w + G * t; i < p.bmw; i += G * WG)
                 clear_rmw(&bm[(uint64_t)op * p.bmw + i]);
         }
         uint32_t act = 0;
@@ -602,6 +602,20 @@ constexpr uint32_t WIDE_NUM = 11, WIDE_DEN = 16;  // widened grid: 11/16 of the 
 constexpr uint32_t WPAR1 = 3;           // window parities
 constexpr double WFRAC1 = 1.5;          // window keys per active swap
 
+// The fresh indices of a round, cursor-1-o for o in [0, take), are dealt to
+// the workgroups in chunks of FRESH_CHUNK consecutive indices, round robin:
+// the j-th fresh index of workgroup w is o = fresh_ord(w, j, G).  Dealing
+// whole blocks (workgroup 0 the top block) made the workgroups holding the
+// highest-priority fresh swaps win, and so move records, more than the
+// others, and the barrier waited for them; chunks keep a chunk's records in
+// one or a few cache lines.
+constexpr uint32_t FRESH_CHUNK = 8;
+
+__device__ __forceinline__ uint32_t fresh_ord(uint32_t w, uint32_t j, uint32_t G)
+{
+    return FRESH_CHUNK * (w + G * (j / FRESH_CHUNK)) + j % FRESH_CHUNK;
+}
+
 template <int EB>
 __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
 {
@@ -625,11 +639,16 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
     uint64_t attempts = 0, retries = 0, selfl = 0, maxact = 0, throttled = 0;
     bool failed = false;
     uint32_t q = (uint32_t)min<uint64_t>(((uint64_t)p.k + G - 1) / G, (uint64_t)WG1);
+    q = max(q / FRESH_CHUNK, 1u) * FRESH_CHUNK;
     uint32_t take = (uint32_t)min<uint64_t>((uint64_t)G * q, p.n);
     uint32_t top = EMPTY;         // rank of the top active swap of the round to check
     uint64_t prevA = 0;           // active swaps of the round checked last
     const double rG = 1.0 / (double)G;
 
+    // what the last barrier gathered: active swaps, swaps just committed,
+    // the fullest workgroup's active swaps, the oldest active rank
+    uint64_t g_act = 0, g_won = 0;
+    uint32_t g_maxa = 0, g_age = 0;
     for (;;) {
         // ---- check round rr-1: issue the loads the decision needs
         const bool act = src != EMPTY;
@@ -641,10 +660,41 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
             q1 = ds < W ? ld(&bm[(uint64_t)par * p.bmw + (ds >> 5)])
                         : ld(&slots[slot1(src, p.T)]);
         }
+        if (rr > 0) {
+            // ---- quota of this refill (the same in every workgroup): the
+            // active swaps that will remain after the check are estimated
+            // from the last check's win rate, and the quota refills them to
+            // k.  (All counts are below 2^32; the quotients are taken in
+            // double precision, which every workgroup evaluates identically
+            // and which is exact for these magnitudes.)
+            top = g_act ? g_age : EMPTY;
+            const uint32_t a32 = (uint32_t)g_act;
+            const uint32_t expect_w =
+                prevA ? (uint32_t)((double)g_act * (double)g_won / (double)prevA) : a32 / 2u;
+            prevA = g_act;
+            const uint32_t want = p.k + expect_w > a32 ? p.k + expect_w - a32 : 0u;
+            // Whole chunks of FRESH_CHUNK (see fresh_ord): the target rounded
+            // to the nearest chunk, the limits rounded down.
+            constexpr uint32_t C = FRESH_CHUNK;
+            uint32_t qq = ((uint32_t)std::ceil((double)want * rG) + C / 2) / C * C;
+            qq = min(qq, ((uint32_t)WG1 - g_maxa) / C * C);
+            const uint32_t room =
+                g_age < p.rank_cap ? (uint32_t)((double)(p.rank_cap - g_age) * rG) / C * C : 0u;
+            if (qq > room) {
+                qq = room;
+                throttled++;
+            }
+            if (qq == 0 && g_act == 0 && cursor > 0)
+                qq = C;
+            q = qq;
+            take = (uint32_t)min<uint64_t>((uint64_t)G * q, cursor);
+        }
         // ---- meanwhile: targets of this workgroup's fresh indices
-        const uint32_t base_w = w * q;
-        if (t < q && base_w + t < take)
-            sh_h[t] = target_of(p, cursor - 1u - (base_w + t));
+        if (t < q) {
+            const uint32_t o = fresh_ord(w, t, G);
+            if (o < take)
+                sh_h[t] = target_of(p, cursor - 1u - o);
+        }
         // ---- decide (the records are not needed for it; winners move them
         // while the refill and the reservations proceed)
         uint32_t won = 0;
@@ -689,8 +739,9 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         for (int i = 0; i < WAVES1; i++)
             below += ((uint32_t)i < wave) ? sh_scan[i] : 0u;
         const uint32_t j = below + lane_rank(fb);
-        if (f && j < q && base_w + j < take) {
-            const uint32_t s = cursor - 1u - (base_w + j);
+        const uint32_t oj = fresh_ord(w, j, G);
+        if (f && j < q && oj < take) {
+            const uint32_t s = cursor - 1u - oj;
             const uint32_t h = sh_h[j];
             if (h == s) {
                 selfl++;
@@ -711,7 +762,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
                 failed = true;
                 break;
             }
-            for (uint32_t i = w * WG1 + t; i < p.T; i += G * WG1)
+            for (uint32_t i = w + G * t; i < p.T; i += G * WG1)
                 clear_rmw(&slots[i]);
             if (!plain_barrier(p, ++epoch, sh_res)) {
                 failed = true;
@@ -721,7 +772,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         // ---- reserve round rr
         {
             const uint32_t cp = (uint32_t)((rr + 1) % WPAR1);
-            for (uint32_t i = w * WG1 + t; i < p.bmw; i += G * WG1)
+            for (uint32_t i = w + G * t; i < p.bmw; i += G * WG1)
                 clear_rmw(&bm[(uint64_t)cp * p.bmw + i]);
         }
         if (src != EMPTY) {
@@ -749,7 +800,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         const bool a = src != EMPTY;
         const uint32_t xw = ((uint32_t)__popcll(__ballot(a)) << 16) |
                             (uint32_t)__popcll(__ballot(won != 0));
-        const uint32_t agew = wave_max(a ? src - cursor : 0u);
+        const uint32_t agew = wave_max_dpp(a ? src - cursor : 0u);
         if (lane == 0)
             sh_pay[wave] = xw;
         if (lane == 0)
@@ -774,17 +825,19 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
                 totW = wgx & 0xFFFFu;
                 agemax = wgage;
             } else {
+                uint32_t sa = 0, sw = 0;
                 ok = gather_wave0(p, epoch, pay, [&](uint32_t, uint64_t y) {
                     const uint32_t av = (uint32_t)(y >> 34) & 0x3FFFu;
-                    totA += av;
-                    totW += (uint32_t)(y >> 24) & 0x3FFu;
+                    sa += av;
+                    sw += (uint32_t)(y >> 24) & 0x3FFu;
                     maxA = max(maxA, av);
                     agemax = max(agemax, (uint32_t)y & RANKMAX);
                 });
-                totA = wave_sum64(totA);
-                totW = wave_sum64(totW);
-                maxA = wave_max(maxA);
-                agemax = wave_max(agemax);
+                // (sums of at most 2048 workgroups of 512 lanes fit 32 bits)
+                totA = wave_sum_dpp(sa);
+                totW = wave_sum_dpp(sw);
+                maxA = wave_max_dpp(maxA);
+                agemax = wave_max_dpp(agemax);
             }
             if (lane == 0) {
                 sh_res[0] = totA;
@@ -799,10 +852,12 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
             failed = true;
             break;
         }
-        const uint64_t totA = sh_res[0], totW = sh_res[1];
-        const uint32_t maxA = (uint32_t)sh_res[2], agemax = (uint32_t)sh_res[4];
-        maxact = max(maxact, totA);
-        if (cursor == 0 && totA == 0)
+        g_act = sh_res[0];
+        g_won = sh_res[1];
+        g_maxa = (uint32_t)sh_res[2];
+        g_age = (uint32_t)sh_res[4];
+        maxact = max(maxact, g_act);
+        if (cursor == 0 && g_act == 0)
             break;
         if (rr > p.max_rounds) {
             if (t == 0)
@@ -810,29 +865,6 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
             failed = true;
             break;
         }
-        // ---- quota of the next refill (the same in every workgroup): the
-        // active swaps that will remain after the coming check are estimated
-        // from the last check's win rate, and the quota refills them to k.
-        // (All counts are below 2^32; the quotients are taken in double
-        // precision, which every workgroup evaluates identically and which
-        // is exact for these magnitudes.)
-        top = totA ? agemax : EMPTY;
-        const uint32_t a32 = (uint32_t)totA;
-        const uint32_t expect_w =
-            prevA ? (uint32_t)((double)totA * (double)totW / (double)prevA) : a32 / 2u;
-        prevA = totA;
-        const uint32_t want = p.k + expect_w > a32 ? p.k + expect_w - a32 : 0u;
-        uint32_t qq = min((uint32_t)std::ceil((double)want * rG), (uint32_t)WG1 - maxA);
-        const uint32_t room =
-            agemax < p.rank_cap ? (uint32_t)((double)(p.rank_cap - agemax) * rG) : 0u;
-        if (qq > room) {
-            qq = room;
-            throttled++;
-        }
-        if (qq == 0 && totA == 0 && cursor > 0)
-            qq = 1;
-        q = qq;
-        take = (uint32_t)min<uint64_t>((uint64_t)G * q, cursor);
     }
 
     // ---- statistics

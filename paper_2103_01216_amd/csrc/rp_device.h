@@ -226,6 +226,32 @@ __device__ __forceinline__ void swap_generic(unsigned char *A, uint32_t eb,
     }
 }
 
+// Reductions over the 64 lanes of a (converged) wave with DPP moves: quad
+// permutes, half-row and row mirrors, then the two row broadcasts; the
+// result forms in lane 63 and is read back as a uniform value.  A few VALU
+// cycles per step instead of a cross-lane permute through LDS.
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_reduce_dpp(uint32_t v, Op op)
+{
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_dpp(uint32_t v)
+{
+    return wave_reduce_dpp(v, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
+__device__ __forceinline__ uint32_t wave_max_dpp(uint32_t v)
+{
+    return wave_reduce_dpp(v, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+}
+
 // Number of lanes below this one whose bit is set in the wave mask m.
 __device__ __forceinline__ uint32_t lane_rank(uint64_t m)
 {
