@@ -51,6 +51,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+COPY_BYTES = 2 << 30            # reference copy of the plain workload
 KERNEL_NAME = "rp_rounds1_kernel"
 WORKLOAD = {"n": 1 << 30, "elem_bytes": 8, "eps": 0.5, "seed": 1}
 BATCH = {"count": 4096, "lo_log2": 8, "hi_log2": 20, "size_seed": 12345,
@@ -200,6 +201,29 @@ def random_access_floor(rp, A, eb, stream, log, reps=3):
     return ms
 
 
+def reference_copy(rp, stream, log, nbytes=COPY_BYTES):
+    """Median time of a streaming copy of `nbytes` (rp_probe_copy): the
+    achievable HBM rate, and the known byte count that scales the rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters of the same run."""
+    import torch
+    src = torch.zeros(nbytes // 8, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    ts = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rp.rp_probe_copy(dst, src, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = sorted(ts)[1]
+    log(f"reference copy: {nbytes / 2**30:.0f} GiB in {ms:.2f} ms "
+        f"({2 * nbytes / (ms * 1e-3) / 1e9:.0f} GB/s read+write)")
+    del src, dst
+    torch.cuda.empty_cache()
+    return ms
+
+
 def serve_leg(rp, rate, duration, log):
     """A short served run at one Poisson rate, batched server against one
     plain launch per request, on the same trace (the serving workload's
@@ -242,6 +266,7 @@ def run_plain(args, log):
     torch.cuda.synchronize()
     log(f"allocated A: n=2^30 int64 ({A.numel() * 8 / 2**30:.0f} GiB)")
     floor_ms = random_access_floor(rp, A, eb, stream, log)
+    copy_ms = reference_copy(rp, stream, log)
     A.copy_(torch.arange(n, dtype=torch.int64, device=dev))
     torch.cuda.synchronize()
 
@@ -342,6 +367,8 @@ def run_plain(args, log):
                      if traffic else None,
                      "kernel": KERNEL_NAME, "kernel_ms_events": ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "reference_copy_bytes": COPY_BYTES,
+                     "reference_copy_gbps": 2 * COPY_BYTES / (copy_ms * 1e-3) / 1e9,
                      "random_access_floor_ms": floor_ms,
                      "random_access_floor_gbps": floor_gbps,
                      "frac_of_random_access_floor": floor_ms / ms},
@@ -927,6 +954,7 @@ def run_scale(args, log):
                      "elements_per_s": n / (ms * 1e-3), "algorithmic_gbps": gbps,
                      "frac_of_peak": gbps / HBM_PEAK_GBPS, "rounds": st["rounds"],
                      "round_us": ms * 1e3 / max(1, st["rounds"]), "k": st["k"],
+                     "max_active": st["max_active"], "inflight_words": st["inflight_words"],
                      "aux_words": st["aux_words"], "aux_bound_words": st["aux_bound_words"],
                      "grid": st["grid"], "slots_per_lane": st["slots_per_lane"]})
         log(f"{label} eps {eps:.3f}: {ms:.1f} ms, {n / (ms * 1e-3):.3g} el/s, {gbps:.0f} GB/s "

@@ -119,6 +119,7 @@ struct Params {
     uint64_t *R64;       // RP_VARIANT_LINEAR: one priority word per position
     uint32_t wg_first;   // this shuffle's workgroups: [wg_first, wg_first + wg_count)
     uint32_t wg_count;   // of the launch (all of it, except in a group launch)
+    uint32_t chunk_log2; // one-barrier kernel: fresh indices are dealt in chunks of 2^this
 };
 
 // rp_stats word indices
@@ -603,17 +604,18 @@ constexpr uint32_t WPAR1 = 3;           // window parities
 constexpr double WFRAC1 = 1.5;          // window keys per active swap
 
 // The fresh indices of a round, cursor-1-o for o in [0, take), are dealt to
-// the workgroups in chunks of FRESH_CHUNK consecutive indices, round robin:
-// the j-th fresh index of workgroup w is o = fresh_ord(w, j, G).  Dealing
-// whole blocks (workgroup 0 the top block) made the workgroups holding the
-// highest-priority fresh swaps win, and so move records, more than the
-// others, and the barrier waited for them; chunks keep a chunk's records in
-// one or a few cache lines.
-constexpr uint32_t FRESH_CHUNK = 8;
+// the workgroups in chunks of C = 2^chunk_log2 consecutive indices, round
+// robin: the j-th fresh index of workgroup w is o = fresh_ord(w, j, G, c).
+// Dealing whole blocks (workgroup 0 the top block) made the workgroups
+// holding the highest-priority fresh swaps win, and so move records, more
+// than the others; chunks keep a chunk's records in one or a few cache lines.
+// Quotas are whole chunks, so the planner keeps G * C within k / 16 (the
+// active total then stays within a few percent of k).
+constexpr uint32_t MAX_CHUNK_LOG2 = 3;
 
-__device__ __forceinline__ uint32_t fresh_ord(uint32_t w, uint32_t j, uint32_t G)
+__device__ __forceinline__ uint32_t fresh_ord(uint32_t w, uint32_t j, uint32_t G, uint32_t cl)
 {
-    return FRESH_CHUNK * (w + G * (j / FRESH_CHUNK)) + j % FRESH_CHUNK;
+    return ((w + G * (j >> cl)) << cl) + (j & ((1u << cl) - 1u));
 }
 
 template <int EB>
@@ -639,7 +641,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
     uint64_t attempts = 0, retries = 0, selfl = 0, maxact = 0, throttled = 0;
     bool failed = false;
     uint32_t q = (uint32_t)min<uint64_t>(((uint64_t)p.k + G - 1) / G, (uint64_t)WG1);
-    q = max(q / FRESH_CHUNK, 1u) * FRESH_CHUNK;
+    q = max(q >> p.chunk_log2, 1u) << p.chunk_log2;
     uint32_t take = (uint32_t)min<uint64_t>((uint64_t)G * q, p.n);
     uint32_t top = EMPTY;         // rank of the top active swap of the round to check
     uint64_t prevA = 0;           // active swaps of the round checked last
@@ -673,9 +675,9 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
                 prevA ? (uint32_t)((double)g_act * (double)g_won / (double)prevA) : a32 / 2u;
             prevA = g_act;
             const uint32_t want = p.k + expect_w > a32 ? p.k + expect_w - a32 : 0u;
-            // Whole chunks of FRESH_CHUNK (see fresh_ord): the target rounded
-            // to the nearest chunk, the limits rounded down.
-            constexpr uint32_t C = FRESH_CHUNK;
+            // Whole chunks (see fresh_ord): the target rounded to the nearest
+            // chunk, the limits rounded down.
+            const uint32_t C = 1u << p.chunk_log2;
             uint32_t qq = ((uint32_t)std::ceil((double)want * rG) + C / 2) / C * C;
             qq = min(qq, ((uint32_t)WG1 - g_maxa) / C * C);
             const uint32_t room =
@@ -691,7 +693,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         }
         // ---- meanwhile: targets of this workgroup's fresh indices
         if (t < q) {
-            const uint32_t o = fresh_ord(w, t, G);
+            const uint32_t o = fresh_ord(w, t, G, p.chunk_log2);
             if (o < take)
                 sh_h[t] = target_of(p, cursor - 1u - o);
         }
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         for (int i = 0; i < WAVES1; i++)
             below += ((uint32_t)i < wave) ? sh_scan[i] : 0u;
         const uint32_t j = below + lane_rank(fb);
-        const uint32_t oj = fresh_ord(w, j, G);
+        const uint32_t oj = fresh_ord(w, j, G, p.chunk_log2);
         if (f && j < q && oj < take) {
             const uint32_t s = cursor - 1u - oj;
             const uint32_t h = sh_h[j];
@@ -985,6 +987,7 @@ struct Plan {
     bool single;      // k = 1 path
     bool lds;         // one workgroup: slots and window in dynamic LDS
     bool onebar;      // one barrier per round (rp_rounds1_kernel, WG1 lanes)
+    uint32_t chunk_log2;  // its chunks of fresh indices
     uint32_t G, M, k, T, bmw;
     uint32_t wpar;    // window parities: 2, or 3 with one barrier per round
     uint64_t bound, aux_bytes;
@@ -1123,6 +1126,9 @@ bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t cus, uint64
     if (G < 2 || G > std::min<uint64_t>(MAXG, wg_cap))
         return false;
     pl->onebar = true;
+    pl->chunk_log2 = 0;
+    while (pl->chunk_log2 < MAX_CHUNK_LOG2 && (G << (pl->chunk_log2 + 1)) * 16 <= k)
+        pl->chunk_log2++;
     pl->wpar = WPAR1;
     pl->k = (uint32_t)k;
     pl->G = (uint32_t)G;
@@ -1136,16 +1142,32 @@ bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t cus, uint64
 
 // occ1: workgroups of the one-barrier kernel a compute unit holds, or 0 when
 // that path may not be used (group launches, variants).
+int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], Plan *pl);
+
+// occ1 > 0: the one-barrier kernel may be used; it replaces the two-barrier
+// plan unless that is the sequential loop (k = 1) or one workgroup with its
+// tables in LDS, whose rounds cost only workgroup barriers (n = 2^28 at
+// eps = 0.75: 4.7 s there against 9.0 s for four one-barrier workgroups).
 int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
                 Plan *pl, int occ1 = 0)
+{
+    const int rc = choose_plan2(n, eb, eps, cus, occ_by_m, pl);
+    if (rc != RP_OK || occ1 <= 0 || pl->single || pl->lds)
+        return rc;
+    Plan p1 = *pl;
+    if (choose_plan1(n, eb, pl->bound * 8, (uint64_t)cus, (uint64_t)cus * occ1, &p1))
+        *pl = p1;
+    return RP_OK;
+}
+
+// The two-barrier plan (rounds_body).
+int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], Plan *pl)
 {
     std::memset(pl, 0, sizeof(*pl));
     pl->bound = rp_aux_bound_words(n, eps);
     pl->eb_class = (eb == 4 || eb == 8 || eb == 16) ? (int)eb : 0;
     pl->wpar = 2;
     const uint64_t budget = pl->bound * 8;
-    if (occ1 > 0 && choose_plan1(n, eb, budget, (uint64_t)cus, (uint64_t)cus * occ1, pl))
-        return RP_OK;
     // The persistent path needs k >= 2.
     if (aux_bytes_for(2, 1, nullptr, nullptr) > budget) {
         pl->single = true;
@@ -1490,6 +1512,7 @@ void setup_params(Params &p, const Plan &pl, int variant, bool lds_tab, void *A,
     p.rank_cap = (rank_cap > 0 && (uint32_t)rank_cap < RANKMAX) ? (uint32_t)rank_cap : RANKMAX;
     p.wg_first = 0;
     p.wg_count = pl.G;
+    p.chunk_log2 = pl.chunk_log2;
     unsigned char *cur = base;
     if (variant == RP_VARIANT_LINEAR) {
         p.R64 = reinterpret_cast<uint64_t *>(cur);
