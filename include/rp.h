@@ -54,7 +54,10 @@ extern "C" {
 /*
  * Per-call statistics, written by the device and copied into caller memory
  * (host) when the stream reaches the end of the call.
- *   k                 active-swap capacity per round (the prefix size)
+ *   k                 active swaps per round the call plans for (the prefix
+ *                     size); with one barrier per round the refill aims
+ *                     at k without knowing the round's commits yet, so a
+ *                     round may hold a few more (see max_active)
  *   aux_words         auxiliary memory of the call, in 8-byte words
  *                     (rounded up): the device memory it allocated for
  *                     tables, bitmaps, barrier flags and counters, plus the
@@ -65,15 +68,21 @@ extern "C" {
  *   attempts          swap attempts summed over rounds (self-loops excluded)
  *   retries           attempts that lost and were carried to the next round
  *   max_active        largest number of swaps attempted in one round
+ *                     (rounds, attempts, retries and max_active may differ
+ *                     slightly between runs of one input: a workgroup's
+ *                     reservation for the next round can make a slower
+ *                     workgroup's check lose once more; the permutation
+ *                     itself never differs)
  *   self_loops        swaps with H[i] = i, retired without a reservation
  *   grid, slots_per_lane, table_slots   launch shape and number of 32-bit
  *                     slots of the hashed reservation array
  *   status            RP_OK, or RP_ETIMEOUT if the device watchdog fired
- *   inflight_words    state the k active swaps hold in registers, in 8-byte
+ *   inflight_words    state the active swaps hold in registers (the
+ *                     larger of k and max_active swaps), in 8-byte
  *                     words: per swap its source and target (4 bytes each)
- *                     and, for records of 4, 8 or 16 bytes, both records
- *                     (read ahead of the decision); other record sizes are
- *                     moved after the decision and hold none.  Not device
+ *                     and, for records of 4, 8 or 16 bytes (and 64 with one
+ *                     barrier per round), both records; other record sizes
+ *                     are moved word by word and hold none.  Not device
  *                     memory and not part of aux_words; reported so that the
  *                     whole working set of a round can be compared with the
  *                     bound (Section 4.1 keeps the prefix's H values inside
