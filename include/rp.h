@@ -463,14 +463,33 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
  * arrival order while their arrays fit in the free part of the arena, fills
  * each admitted array on the device, and runs admitted requests as batched
  * launches (the batched form above) that overlap on the device with launches
- * still running.  Each request's result is the Knuth shuffle of its array
- * with its seed, whatever else runs beside it.  One host thread per server
- * does all device work; the calls below only exchange bookkeeping with it and
+ * still running, or through one resident kernel that takes each request as
+ * it arrives.  Each request's result is the Knuth shuffle of its array with
+ * its seed, whatever else runs beside it.  One host thread per server does
+ * all device work; the calls below only exchange bookkeeping with it and
  * never block on the GPU (rp_server_destroy excepted).
+ *
+ * Resident mode: while the server has work, one kernel (one 512-lane
+ * workgroup per compute unit) stays on the device and takes admitted
+ * requests from a ring in host memory as they arrive, so a request starts on
+ * the next free workgroup instead of with the next launch (admission at the
+ * granularity of a workgroup's request boundary).  A request below
+ * 2^large_log2 elements runs on one workgroup with its round state in LDS;
+ * a larger one on a gang of idle workgroups (up to a quarter of them, fewer
+ * while other gangs are posted) that runs the one-barrier rounds with its
+ * tables in the arena, counted against the admission budget and the
+ * auxiliary bound of its eps.  The kernel fills each array itself (identity,
+ * or a copy from device or pinned host memory: rp_server_submit rejects any
+ * other source with RP_EINVAL), leaves 20 ms after the server runs out of
+ * work (every wave reaches a stop word the host sets) and is launched again
+ * when work arrives.  It runs on the server's own stream; device work that
+ * other code puts on a stream sharing its hardware queue may wait until it
+ * leaves.
  * ------------------------------------------------------------------------ */
 
 #define RP_SERVE_BATCHED 0  /* admitted requests go out as batched launches */
 #define RP_SERVE_PLAIN 1    /* one rp_shuffle_inplace per request, in order */
+#define RP_SERVE_RESIDENT 2 /* admitted requests go to a resident kernel */
 
 #define RP_INIT_IDENTITY 0  /* A[i] = i (elem_bytes 4 or 8: the integer i;
                                other sizes: word 0 = i, other words 0) */
@@ -486,10 +505,12 @@ typedef struct rp_server_config {
     uint64_t mem_budget_bytes;   /* arena size: bound on the bytes of all
                                     admitted, unreleased arrays; 0: the
                                     process default (rp_set_mem_budget) */
-    uint32_t mode;               /* RP_SERVE_BATCHED or RP_SERVE_PLAIN */
+    uint32_t mode;               /* RP_SERVE_BATCHED, RP_SERVE_PLAIN or
+                                    RP_SERVE_RESIDENT */
     uint32_t max_batch;          /* requests per launch; 0: no limit */
     uint32_t large_log2;         /* n >= 2^large_log2 uses the large-request
-                                    streams; 0: 22 */
+                                    streams (resident mode: may run on a
+                                    gang); 0: 22 */
     uint32_t tick_us;            /* dispatcher poll interval; 0: 50 */
     uint32_t auto_release;       /* 1: free each array as soon as it is done
                                     (results are not kept) */
@@ -525,7 +546,7 @@ typedef struct rp_server_ticket_info {
     uint64_t t_done_ns;          /* when the dispatcher saw completion */
     void *A;                     /* device array (NULL until admitted, and
                                     after release) */
-    uint64_t rounds;             /* rounds run (batched mode) */
+    uint64_t rounds;             /* rounds run (batched and resident modes) */
     uint32_t aux_words;          /* round-state words used */
     uint32_t reserved;
 } rp_server_ticket_info;

@@ -519,6 +519,7 @@ def rp_batch_autotune(arrays, *, seeds=None, eps: float = 0.5, stream=None) -> d
 
 RP_SERVE_BATCHED = 0
 RP_SERVE_PLAIN = 1
+RP_SERVE_RESIDENT = 2
 RP_INIT_IDENTITY = 0
 RP_INIT_COPY = 1
 RP_REQ_QUEUED, RP_REQ_ADMITTED, RP_REQ_RUNNING, RP_REQ_DONE = 0, 1, 2, 3

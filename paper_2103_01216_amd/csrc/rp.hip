@@ -82,6 +82,8 @@
 
 #include "rp.h"
 #include "rp_device.h"
+#include "rp_resident.h"
+#include "rp_wg.h"
 
 namespace {
 
@@ -135,7 +137,8 @@ __device__ __forceinline__ uint32_t target_of(const Params &p, uint32_t s)
 
 // --------------------------------------------------------------- the gather
 
-// Wave 0 of every workgroup: publish the 48-bit `payload` under `epoch`,
+// Wave 0 of every workgroup (w: its index among the p.wg_count workgroups of
+// the shuffle): publish the 48-bit `payload` under `epoch`,
 // wait for every workgroup's flag of the same epoch and hand each payload to
 // `visit` (lane-strided).  Flags hold epoch:16 | payload:48 and are
 // double-buffered by epoch parity: a workgroup cannot publish epoch e+2
@@ -144,14 +147,14 @@ __device__ __forceinline__ uint32_t target_of(const Params &p, uint32_t s)
 // workgroup's memory operations complete (wait_mem in every wave, then a
 // workgroup barrier) before calling.
 template <typename Visit>
-__device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t epoch,
+__device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t w, uint32_t epoch,
                                              uint64_t payload, Visit visit)
 {
     const uint32_t G = p.wg_count, lane = threadIdx.x & 63;
     const uint32_t e16 = epoch & 0xFFFFu;
     uint64_t *fl = p.flags + (uint64_t)(epoch & 1u) * G;
     if (lane == 0)
-        st(&fl[blockIdx.x - p.wg_first], ((uint64_t)e16 << 48) | payload);
+        st(&fl[w], ((uint64_t)e16 << 48) | payload);
     // Poll every flag this lane covers at once; look at the clock and the
     // error word only every 64 sweeps so that a sweep costs one load latency.
     const int nj = (int)((G + 63u) / 64u);
@@ -199,7 +202,7 @@ __device__ __forceinline__ bool gather_wave0(const Params &p, uint32_t epoch,
 // -------------------------------------------------------------- the kernel
 
 // Barrier with no payload (the periodic reset of the reservation array).
-__device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t epoch,
+__device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t w, uint32_t epoch,
                                               uint64_t *sh_res)
 {
     wait_mem();
@@ -207,7 +210,7 @@ __device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t epoch,
     if ((threadIdx.x >> 6) == 0) {
         bool ok = true;
         if (p.wg_count > 1)
-            ok = gather_wave0(p, epoch, 0, [](uint32_t, uint64_t) {});
+            ok = gather_wave0(p, w, epoch, 0, [](uint32_t, uint64_t) {});
         if ((threadIdx.x & 63) == 0)
             sh_res[3] = ok ? 0u : 1u;
     }
@@ -303,7 +306,7 @@ __device__ __forceinline__ void rounds_body(const Params &p)
             } else {
                 const uint64_t pay = ((uint64_t)(wgtot >> 16) << 36) |
                                      ((uint64_t)(wgtot & 0xFFFFu) << 24) | wgage;
-                ok = gather_wave0(p, epoch, pay, [&](uint32_t v, uint64_t y) {
+                ok = gather_wave0(p, w, epoch, pay, [&](uint32_t v, uint64_t y) {
                     const uint32_t fv = (uint32_t)(y >> 24) & 0xFFFu;
                     pre += (v < w) ? fv : 0u;
                     totF += fv;
@@ -353,7 +356,7 @@ __device__ __forceinline__ void rounds_body(const Params &p)
         if (tag == 0 && rounds > 0 && !linear) {
             for (uint32_t i = w + G * t; i < p.T; i += G * WG)
                 clear_rmw(&slots[i]);
-            if (!plain_barrier(p, ++epoch, sh_res)) {
+            if (!plain_barrier(p, w, ++epoch, sh_res)) {
                 failed = true;
                 break;
             }
@@ -457,7 +460,7 @@ __device__ __forceinline__ void rounds_body(const Params &p)
             if (G == 1)
                 tot = actw;
             else
-                ok = gather_wave0(p, epoch, actw,
+                ok = gather_wave0(p, w, epoch, actw,
                                   [&](uint32_t, uint64_t y) { tot += y; });
             tot = wave_sum64(tot);
             if (lane == 0) {
@@ -618,8 +621,11 @@ __device__ __forceinline__ uint32_t fresh_ord(uint32_t w, uint32_t j, uint32_t G
     return ((w + G * (j >> cl)) << cl) + (j & ((1u << cl) - 1u));
 }
 
+// The rounds of one shuffle on workgroup w of its p.wg_count, with flag
+// epochs counted from `epoch0` (the last epoch used before, on the same
+// flags); returns the last epoch it used.
 template <int EB>
-__global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
+__device__ __forceinline__ uint32_t rounds1_body(const Params &p, uint32_t w, uint32_t epoch0)
 {
     __shared__ uint32_t sh_scan[WAVES1];
     __shared__ uint32_t sh_pay[WAVES1];
@@ -627,14 +633,14 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
     __shared__ uint32_t sh_h[WG1];
     __shared__ uint64_t sh_res[6];
 
-    const uint32_t G = p.wg_count, w = blockIdx.x - p.wg_first, t = threadIdx.x;
+    const uint32_t G = p.wg_count, t = threadIdx.x;
     const uint32_t wave = t >> 6, lane = t & 63;
     const uint32_t W = p.bmw * 32u;
     uint32_t *const slots = p.slots;
     uint32_t *const bm = p.bm;
     using R = Rec<EB == 0 ? 4 : EB>;
 
-    uint32_t epoch = 0;
+    uint32_t epoch = epoch0;
     uint32_t src = EMPTY, tgt = 0;
     uint32_t cursor = p.n;        // rank base of the round last reserved
     uint64_t rr = 0;              // rounds reserved so far
@@ -760,13 +766,13 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         // of the old tags, the second every clear before a reservation with
         // the new ones.
         if (tag == 0 && rr > 0) {
-            if (!plain_barrier(p, ++epoch, sh_res)) {
+            if (!plain_barrier(p, w, ++epoch, sh_res)) {
                 failed = true;
                 break;
             }
             for (uint32_t i = w + G * t; i < p.T; i += G * WG1)
                 clear_rmw(&slots[i]);
-            if (!plain_barrier(p, ++epoch, sh_res)) {
+            if (!plain_barrier(p, w, ++epoch, sh_res)) {
                 failed = true;
                 break;
             }
@@ -828,7 +834,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
                 agemax = wgage;
             } else {
                 uint32_t sa = 0, sw = 0;
-                ok = gather_wave0(p, epoch, pay, [&](uint32_t, uint64_t y) {
+                ok = gather_wave0(p, w, epoch, pay, [&](uint32_t, uint64_t y) {
                     const uint32_t av = (uint32_t)(y >> 34) & 0x3FFFu;
                     sa += av;
                     sw += (uint32_t)(y >> 24) & 0x3FFu;
@@ -893,6 +899,444 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
         }
         if (failed)
             st(&p.dstats[S_STATUS], (uint64_t)(int64_t)RP_ETIMEOUT);
+    }
+    return epoch;
+}
+
+template <int EB>
+__global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
+{
+    (void)rounds1_body<EB>(p, blockIdx.x - p.wg_first, 0u);
+}
+
+// ------------------------------------------------------ the resident kernel
+//
+// A kernel that stays on the device while a server has work, and takes each
+// request from the server's ring (rp_resident.h) as it arrives: a request
+// starts as soon as a workgroup is free, at that workgroup's next request
+// boundary, instead of at the next launch.  Every workgroup loops: claim the
+// next entry in ring order, run it, report it, claim again.
+//   * A request planned for one workgroup runs the workgroup rounds of the
+//     batched form (rp_wg.h), its round state in the workgroup's LDS.
+//   * A request planned for a gang of G workgroups runs the one-barrier
+//     rounds above on G workgroups, its tables in device memory the server
+//     allocated with it.  The workgroup that claims it (the leader) opens the
+//     gang, idle workgroups join it before they claim anything else, and all
+//     start once G have joined: every member is then running, so its flag
+//     barriers complete.  One gang forms at a time.  A leader whose gang has
+//     not formed within form_ticks closes it and reports the request as not
+//     run, and the server posts it again.
+//   * One workgroup at a time reads the host ring for new entries and
+//     publishes what it finds (and the host's stop word) in device memory;
+//     the other idle workgroups poll only device memory.
+//   * The kernel ends when the host sets the stop word (every workgroup
+//     finishes its request first), or by itself after idle_ticks with
+//     nothing to claim.
+constexpr uint32_t RES_WG = WG1;          // the one-barrier body's workgroup
+using ResShape = rpwg::Shape<RES_WG>;
+constexpr uint32_t RES_MASK = rpres::RING - 1;
+
+struct ResCtl {
+    uint64_t head;          // next entry to claim
+    uint64_t avail;         // entries below this are known to be posted
+    uint64_t gang;          // forming gang: (entry + 1) << 24 | need << 12 | joined;
+                            // joined = 0 while its leader is still claiming it
+    uint32_t poll_owner;    // 1 while a workgroup reads the host ring
+    uint32_t gang_left;     // members of the full gang that have seen it full
+    uint32_t exitf;         // 1: claim nothing more and leave
+    uint32_t pad[9];
+    uint32_t need[rpres::RING];             // workgroups each posted entry needs
+    uint64_t stats[rpres::RING][S_WORDS];   // a gang's statistics, per ring slot
+};
+
+struct ResParams {
+    const rpres::Entry *ring;
+    rpres::Result *res;
+    const uint32_t *stop;
+    ResCtl *ctl;
+    uint64_t idle_ticks;
+    uint64_t form_ticks;
+};
+
+enum : uint32_t { RCMD_EXIT = 0, RCMD_SINGLE = 1, RCMD_LEAD = 2, RCMD_JOIN = 3 };
+
+template <typename T>
+__device__ __forceinline__ T ld_sys(const T *p)
+{
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_sys(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename T>
+__device__ __forceinline__ bool cas_agent(T *p, T expect, T v)
+{
+    return __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T xchg_agent(T *p, T v, int order = __ATOMIC_RELAXED)
+{
+    return order == __ATOMIC_RELEASE
+               ? __hip_atomic_exchange(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT)
+               : __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t now_ticks()
+{
+    return __builtin_amdgcn_s_memrealtime();
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t rfl64(uint64_t v)
+{
+    return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
+}
+
+// Thread 0: what this workgroup does next.  A forming gang takes idle
+// workgroups first; then the next posted entry is claimed; with nothing
+// posted that is known, one workgroup at a time reads the host ring.
+__device__ __forceinline__ uint32_t res_next(const ResParams &P, uint64_t *entry, uint32_t *rank)
+{
+    ResCtl *c = P.ctl;
+    uint64_t t_last = now_ticks();
+    for (;;) {
+        const uint64_t W = ld(&c->gang);
+        if (W != 0) {
+            const uint32_t joined = (uint32_t)W & 0xFFFu;
+            const uint32_t need = (uint32_t)(W >> 12) & 0xFFFu;
+            if (joined != 0 && joined < need) {
+                if (cas_agent(&c->gang, W, W + 1)) {
+                    *entry = (W >> 24) - 1;
+                    *rank = joined;
+                    return RCMD_JOIN;
+                }
+                continue;
+            }
+            // locked by its leader or full: either lasts microseconds
+            if (now_ticks() - t_last > P.idle_ticks) {
+                (void)xchg_agent(&c->exitf, 1u);
+                return RCMD_EXIT;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        if (ld(&c->exitf) != 0u)
+            return RCMD_EXIT;
+        const uint64_t h = ld(&c->head);
+        const uint64_t a = __hip_atomic_load(&c->avail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < a) {
+            const uint32_t nd = ld(&c->need[h & RES_MASK]);
+            if (nd <= 1u) {
+                if (cas_agent(&c->head, h, h + 1)) {
+                    *entry = h;
+                    *rank = 0;
+                    return RCMD_SINGLE;
+                }
+                continue;
+            }
+            // A gang entry is claimed with the gang word locked for it, so
+            // no workgroup joins before its leader owns the entry.
+            const uint64_t Wl = ((h + 1) << 24) | ((uint64_t)nd << 12);
+            if (cas_agent(&c->gang, (uint64_t)0, Wl)) {
+                if (cas_agent(&c->head, h, h + 1)) {
+                    *entry = h;
+                    *rank = 0;
+                    return RCMD_LEAD;
+                }
+                (void)xchg_agent(&c->gang, (uint64_t)0);  // h was stale; nobody joined
+            }
+            continue;
+        }
+        if (ld(&c->poll_owner) == 0u && xchg_agent(&c->poll_owner, 1u) == 0u) {
+            uint64_t aa = a;
+            while (aa - h < rpres::RING) {
+                const rpres::Entry *e = &P.ring[aa & RES_MASK];
+                if (__hip_atomic_load(const_cast<uint64_t *>(&e->seq), __ATOMIC_ACQUIRE,
+                                      __HIP_MEMORY_SCOPE_SYSTEM) != aa + 1)
+                    break;
+                st(&c->need[aa & RES_MASK], ld_sys(&e->gang));
+                aa++;
+            }
+            if (aa > a)
+                (void)__hip_atomic_fetch_max(&c->avail, aa, __ATOMIC_RELEASE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            const bool stop = ld_sys(P.stop) != 0u;
+            if (stop)
+                (void)xchg_agent(&c->exitf, 1u);
+            (void)xchg_agent(&c->poll_owner, 0u, __ATOMIC_RELEASE);
+            if (aa > a) {
+                t_last = now_ticks();
+                continue;
+            }
+            if (stop)
+                return RCMD_EXIT;
+        }
+        if (now_ticks() - t_last > P.idle_ticks) {
+            (void)xchg_agent(&c->exitf, 1u);
+            return RCMD_EXIT;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+// Thread 0 of a gang member: wait until the gang of entry `e` has all `need`
+// members.  The last member to see it full clears the gang word for the next
+// gang.  The leader closes a gang that has not formed within form_ticks;
+// then every member returns false.
+__device__ __forceinline__ bool res_gang_wait(const ResParams &P, uint64_t e, uint32_t need,
+                                              bool leader)
+{
+    ResCtl *c = P.ctl;
+    const uint64_t id = ((e + 1) << 12) | need;
+    const uint64_t t0 = now_ticks();
+    for (;;) {
+        const uint64_t W = ld(&c->gang);
+        if ((W >> 12) != id)
+            return false;   // closed before it filled
+        if ((uint32_t)(W & 0xFFFu) == need) {
+            if (__hip_atomic_fetch_add(&c->gang_left, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) + 1u == need) {
+                (void)xchg_agent(&c->gang_left, 0u);
+                (void)xchg_agent(&c->gang, (uint64_t)0, __ATOMIC_RELEASE);
+            }
+            return true;
+        }
+        if (leader && now_ticks() - t0 > P.form_ticks && cas_agent(&c->gang, W, (uint64_t)0))
+            return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Thread 0: report a ring slot's result; the records (and the result) are
+// made visible beyond the device before the completion word.
+__device__ __forceinline__ void res_publish(rpres::Result *out, uint64_t seq, uint64_t rounds,
+                                            uint64_t attempts, int32_t status)
+{
+    st_sys(&out->rounds, rounds);
+    st_sys(&out->attempts, attempts);
+    st_sys(&out->status, status);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    st_sys(&out->done, seq);
+}
+
+// Records [first, n) stepping by `step`: A[r] = r (word 0 of a wider record,
+// the other words 0), or a copy of src.  Coherent: device-scope stores, for
+// a gang whose members on other compute units read the records next.  The
+// source is read with system-scope loads: the kernel outlives the writes
+// that produced it, so its caches may hold older copies of those lines.
+template <bool COHERENT>
+__device__ void res_fill(unsigned char *A, const void *src, uint32_t n, uint32_t eb,
+                         uint32_t fill, uint64_t first, uint64_t step)
+{
+    if (fill == rpres::FILL_NONE)
+        return;
+    const bool copy = fill == rpres::FILL_COPY;
+    for (uint64_t r = first; r < n; r += step) {
+        if ((eb & 7u) == 0) {
+            uint64_t *d = reinterpret_cast<uint64_t *>(A + r * eb);
+            const uint64_t *s = reinterpret_cast<const uint64_t *>(
+                static_cast<const unsigned char *>(src) + r * eb);
+            for (uint32_t w = 0; w < eb / 8; w++) {
+                const uint64_t v = copy ? ld_sys(s + w) : (w == 0 ? r : 0ull);
+                if (COHERENT) st(d + w, v); else rpwg::as_global(d)[w] = v;
+            }
+        } else {
+            uint32_t *d = reinterpret_cast<uint32_t *>(A + r * eb);
+            const uint32_t *s = reinterpret_cast<const uint32_t *>(
+                static_cast<const unsigned char *>(src) + r * eb);
+            for (uint32_t w = 0; w < eb / 4; w++) {
+                const uint32_t v = copy ? ld_sys(s + w) : (w == 0 ? (uint32_t)r : 0u);
+                if (COHERENT) st(d + w, v); else rpwg::as_global(d)[w] = v;
+            }
+        }
+    }
+}
+
+// (Flattened: calls would pass the request through scratch memory.)
+__global__ __launch_bounds__(RES_WG) __attribute__((flatten)) void
+rp_resident_kernel(ResParams P)
+{
+    __shared__ uint32_t lds[ResShape::LDS_WORDS];
+    __shared__ uint32_t sh_scan[ResShape::WAVES];
+    __shared__ uint64_t sh_red[ResShape::WAVES];
+    __shared__ uint64_t sh_res[6];
+    __shared__ uint64_t sh_e[sizeof(rpres::Entry) / 8];
+    __shared__ uint64_t sh_idx;
+    __shared__ uint32_t sh_cmd, sh_rank, sh_go;
+
+    const uint32_t t = threadIdx.x;
+    // Every value that steers these loops is made wave-uniform, and each
+    // single-lane step is closed by a workgroup barrier before the loop's
+    // back edge.
+    for (;;) {
+        if (t == 0) {
+            uint64_t idx = 0;
+            uint32_t rank = 0;
+            const uint32_t cmd = res_next(P, &idx, &rank);
+            if (cmd != RCMD_EXIT) {
+                const uint64_t *q = reinterpret_cast<const uint64_t *>(&P.ring[idx & RES_MASK]);
+                for (uint32_t i = 0; i < sizeof(rpres::Entry) / 8; i++)
+                    sh_e[i] = ld_sys(q + i);
+            }
+            sh_cmd = cmd;
+            sh_idx = idx;
+            sh_rank = rank;
+        }
+        __syncthreads();
+        const uint32_t cmd = rfl(sh_cmd);
+        if (cmd == RCMD_EXIT)
+            break;
+        const uint64_t idx = rfl64(sh_idx);
+        const uint32_t rank = rfl(sh_rank);
+        const rpres::Entry &le = *reinterpret_cast<const rpres::Entry *>(sh_e);
+        unsigned char *const A = reinterpret_cast<unsigned char *>(rfl64((uint64_t)le.A));
+        unsigned char *const aux = reinterpret_cast<unsigned char *>(rfl64((uint64_t)le.aux));
+        const void *const src = reinterpret_cast<const void *>(rfl64((uint64_t)le.src));
+        const uint64_t seed = rfl64(le.seed), max_rounds = rfl64(le.max_rounds);
+        const uint32_t n = rfl(le.n), eb = rfl(le.eb), k = rfl(le.k), T = rfl(le.T),
+                       bmw = rfl(le.bmw), G = rfl(le.gang), cl = rfl(le.chunk_log2),
+                       rank_cap = rfl(le.rank_cap), fill = rfl(le.fill);
+        const uint64_t seq = idx + 1;
+        rpres::Result *const out = &P.res[idx & RES_MASK];
+        __syncthreads();
+
+        if (cmd == RCMD_SINGLE) {
+            if (t == 0)
+                st_sys(&out->started, seq);
+            res_fill<false>(A, src, n, eb, fill, t, RES_WG);
+            __syncthreads();
+            const rpwg::BatchReq r{A, nullptr, seed, n, eb, k, T, bmw, 1u,
+                                   (uint32_t)(idx & RES_MASK), 0u};
+            rpwg::WGGroup<RES_WG> wg;
+            wg.lds = lds;
+            wg.sh_scan = sh_scan;
+            uint64_t rounds = 0, attempts = 0;
+            uint32_t status = 0;
+            if (n > 1) {
+                if (eb == 4)
+                    rpwg::run_request<4>(wg, r, max_rounds, false, &rounds, &attempts, &status);
+                else if (eb == 8)
+                    rpwg::run_request<8>(wg, r, max_rounds, false, &rounds, &attempts, &status);
+                else
+                    rpwg::run_request<0>(wg, r, max_rounds, false, &rounds, &attempts, &status);
+            }
+            attempts = rpwg::sum_over_group_wg<ResShape::WAVES>(attempts, sh_red);
+            rounds = rpwg::sum_over_group_wg<ResShape::WAVES>(
+                T == 0 ? rounds : (t == 0 ? rounds : 0), sh_red);
+            if (t == 0)
+                res_publish(out, seq, rounds, attempts, status ? -(int32_t)status : RP_OK);
+            __syncthreads();
+            continue;
+        }
+
+        // ---- a gang of G workgroups; this one is member `rank`
+        Params p{};
+        p.A = A;
+        p.H = nullptr;
+        p.seed = seed;
+        p.n = n;
+        p.eb = eb;
+        p.k = k;
+        p.T = T;
+        p.bmw = bmw;
+        p.choices = 1;
+        p.variant = RP_VARIANT_FINAL;
+        p.lds_tab = 0;
+        p.R64 = nullptr;
+        p.max_rounds = max_rounds;
+        p.rank_cap = rank_cap;
+        p.wg_first = 0;
+        p.wg_count = G;
+        p.chunk_log2 = cl;
+        // the layout of aux_bytes_for1: slots, three window parities, the
+        // gather flags, the error word
+        unsigned char *cur = aux;
+        p.slots = reinterpret_cast<uint32_t *>(cur);
+        cur += ((uint64_t)T * 4 + 7) / 8 * 8;
+        p.bm = reinterpret_cast<uint32_t *>(cur);
+        cur += ((uint64_t)WPAR1 * bmw * 4 + 7) / 8 * 8;
+        p.flags = reinterpret_cast<uint64_t *>(cur);
+        cur += 2ull * G * 8;
+        p.err = reinterpret_cast<uint32_t *>(cur);
+        p.dstats = P.ctl->stats[idx & RES_MASK];
+        if (cmd == RCMD_LEAD) {
+            // Before anyone joins: the words the first barrier and the
+            // statistics start from.
+            if (t == 0)
+                st_sys(&out->started, seq);
+            for (uint32_t i = t; i < 2 * G; i += RES_WG)
+                st(&p.flags[i], (uint64_t)0);
+            if (t == 0)
+                st(p.err, 0u);
+            if (t < S_WORDS)
+                (void)xchg_agent(&p.dstats[t], (uint64_t)0);
+            wait_mem();
+            __syncthreads();
+            if (t == 0)
+                (void)xchg_agent(&P.ctl->gang, ((idx + 1) << 24) | ((uint64_t)G << 12) | 1u,
+                                 __ATOMIC_RELEASE);
+        }
+        if (t == 0)
+            sh_go = res_gang_wait(P, idx, G, cmd == RCMD_LEAD) ? 1u : 0u;
+        __syncthreads();
+        if (rfl(sh_go) == 0u) {
+            if (cmd == RCMD_LEAD && t == 0)
+                res_publish(out, seq, 0, 0, RP_PENDING);
+            __syncthreads();
+            continue;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // This member's share of the input and of the tables, then a
+        // barrier before the first round.
+        res_fill<true>(A, src, n, eb, fill, (uint64_t)rank * RES_WG + t, (uint64_t)G * RES_WG);
+        for (uint32_t i = rank + G * t; i < T; i += G * RES_WG)
+            clear_rmw(&p.slots[i]);
+        for (uint32_t i = rank + G * t; i < WPAR1 * bmw; i += G * RES_WG)
+            clear_rmw(&p.bm[i]);
+        bool ok = plain_barrier(p, rank, 1u, sh_res);
+        if (ok) {
+            uint32_t epoch;
+            switch (eb) {
+            case 4: epoch = rounds1_body<4>(p, rank, 1u); break;
+            case 8: epoch = rounds1_body<8>(p, rank, 1u); break;
+            case 16: epoch = rounds1_body<16>(p, rank, 1u); break;
+            case 64: epoch = rounds1_body<64>(p, rank, 1u); break;
+            default: epoch = rounds1_body<0>(p, rank, 1u); break;
+            }
+            // every member's statistics are in before the leader reads them
+            ok = plain_barrier(p, rank, epoch + 1, sh_res);
+        }
+        if (rank == 0 && t == 0) {
+            int32_t status = (int32_t)(int64_t)ld(&p.dstats[S_STATUS]);
+            if (!ok || ld(p.err) != 0u)
+                status = RP_ETIMEOUT;
+            res_publish(out, seq, ld(&p.dstats[S_ROUNDS]), ld(&p.dstats[S_ATTEMPTS]), status);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void rp_res_init_kernel(ResCtl *c, uint64_t first)
+{
+    // These words are later updated by read-modify-write atomics: reset them
+    // with atomics too.
+    if (threadIdx.x == 0) {
+        (void)xchg_agent(&c->head, first);
+        (void)xchg_agent(&c->avail, first);
+        (void)xchg_agent(&c->gang, (uint64_t)0);
+        (void)xchg_agent(&c->poll_owner, 0u);
+        (void)xchg_agent(&c->gang_left, 0u);
+        (void)xchg_agent(&c->exitf, 0u);
     }
 }
 
@@ -1472,6 +1916,103 @@ int group_grid(uint64_t n, uint32_t elem_bytes, double eps, int device, uint64_t
         return rc;
     *grid = (pl.single || pl.M != 1) ? 0 : pl.G;
     return RP_OK;
+}
+
+uint64_t resident_ctl_bytes()
+{
+    return sizeof(ResCtl);
+}
+
+int resident_grid(int device, uint32_t *grid)
+{
+    DevInfo d;
+    const int rc = device_info(device, &d);
+    if (rc != RP_OK)
+        return rc;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(rp_resident_kernel), RES_WG, 0) != hipSuccess ||
+        occ < 1)
+        return RP_EDEVICE;
+    // One workgroup per compute unit: the rest of each unit stays free for
+    // the device's other work.
+    *grid = (uint32_t)d.cus;
+    return RP_OK;
+}
+
+int resident_plan(uint64_t n, uint32_t eb, double eps, uint32_t max_gang, int device,
+                  bool allow_gang, rpres::Entry *e, uint64_t *aux_bytes)
+{
+    if (e == nullptr || aux_bytes == nullptr || n == 0 || n >= (1ull << 32) ||
+        !(eps > 0.0 && eps < 1.0) || eb == 0 || (eb & 3u) != 0 || eb > 256)
+        return RP_EINVAL;
+    std::memset(e, 0, sizeof(*e));
+    e->n = (uint32_t)n;
+    e->eb = eb;
+    e->max_rounds = n + 64;
+    e->rank_cap = RANKMAX;
+    e->gang = 1;
+    *aux_bytes = 0;
+    const uint64_t gmax = std::min<uint64_t>({(uint64_t)max_gang, rpres::MAX_GANG, MAXG});
+    if (allow_gang && gmax >= 2 && n > 1) {
+        DevInfo d;
+        const int rc = device_info(device, &d);
+        if (rc != RP_OK)
+            return rc;
+        const uint64_t cus = (uint64_t)d.cus;
+        const uint64_t budget = rp_aux_bound_words(n, eps) * 8;
+        // The largest k whose tables fit the bound on a gang of
+        // min(grid1_for(k), gmax) workgroups with room for every workgroup's
+        // quota (true up to some k, false beyond it).
+        auto gang_for = [&](uint64_t k) { return std::min<uint64_t>(grid1_for(k, cus), gmax); };
+        auto fits = [&](uint64_t k) {
+            const uint64_t G = gang_for(k);
+            return G * WG1 >= 2 * k && aux_bytes_for1(k, G, cus, nullptr, nullptr, nullptr) <= budget;
+        };
+        uint64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) / 2;
+            if (fits(mid)) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint64_t k = lo, G = gang_for(k);
+        if (k >= 2 && G >= 2) {
+            uint64_t T, bmw, Gx;
+            const uint64_t aux = aux_bytes_for1(k, G, cus, &T, &bmw, &Gx);
+            uint32_t cl = 0;
+            while (cl < MAX_CHUNK_LOG2 && (G << (cl + 1)) * 16 <= k)
+                cl++;
+            e->gang = (uint32_t)G;
+            e->k = (uint32_t)k;
+            e->T = (uint32_t)T;
+            e->bmw = (uint32_t)bmw;
+            e->chunk_log2 = cl;
+            e->aux_words = (uint32_t)((aux + 7) / 8);
+            *aux_bytes = aux;
+            return RP_OK;
+        }
+    }
+    uint32_t k, T, bmw;
+    rpwg::plan_request(n, eps, 1.0, RES_WG, ResShape::LDS_WORDS, &k, &T, &bmw);
+    e->k = k;
+    e->T = T;
+    e->bmw = bmw;
+    e->aux_words = (uint32_t)(((uint64_t)(T + 2 * bmw) * 4 + 7) / 8);
+    return RP_OK;
+}
+
+int resident_launch(const rpres::Launch &L, hipStream_t stream)
+{
+    if (L.ring == nullptr || L.res == nullptr || L.stop == nullptr || L.ctl == nullptr ||
+        L.grid == 0)
+        return RP_EINVAL;
+    ResCtl *c = static_cast<ResCtl *>(L.ctl);
+    hipLaunchKernelGGL(rp_res_init_kernel, dim3(1), dim3(64), 0, stream, c, L.first);
+    if (hipGetLastError() != hipSuccess)
+        return RP_EDEVICE;
+    ResParams P{L.ring, L.res, L.stop, c, L.idle_ticks, L.form_ticks};
+    hipLaunchKernelGGL(rp_resident_kernel, dim3(L.grid), dim3(RES_WG), 0, stream, P);
+    return hipGetLastError() == hipSuccess ? RP_OK : RP_EDEVICE;
 }
 
 }  // namespace rpint
@@ -2060,7 +2601,7 @@ __global__ __launch_bounds__(WG) void rp_probe_barrier_kernel(Params p, uint32_t
 {
     __shared__ uint64_t sh_res[5];
     for (uint32_t r = 0; r < rounds; r++)
-        if (!plain_barrier(p, r + 1, sh_res))
+        if (!plain_barrier(p, blockIdx.x, r + 1, sh_res))
             return;
 }
 

@@ -12,6 +12,10 @@
 //     others run starts as soon as a stream is free and finishes on its own
 //     completion flag, not with its launch.  Large requests (n >= 2^large_log2)
 //     have their own streams so that small ones never queue behind them;
+//   * resident mode: one kernel stays on the device while there is work and
+//     takes each admitted request from a ring in host memory as it arrives
+//     (rp_resident.h): a small request starts on the next free workgroup, a
+//     large one on a gang of idle workgroups, without waiting for a launch;
 //   * plain mode: one rp_shuffle_inplace per request, in admission order, on
 //     one stream (the per-request path the batched mode is measured against).
 // One dispatcher thread does all device work; the C entry points only exchange
@@ -28,11 +32,13 @@
 #include <mutex>
 #include <set>
 #include <cstddef>
+#include <cstdlib>
 #include <thread>
 #include <vector>
 
 #include "rp.h"
 #include "rp_arena.h"
+#include "rp_resident.h"
 
 namespace rpint {
 // rp.hip: workgroups rp_shuffle_group gives one shuffle (0: not groupable).
@@ -47,6 +53,13 @@ constexpr int N_STREAMS = N_SMALL_STREAMS + N_LARGE_STREAMS;
 constexpr uint32_t PLAIN_AHEAD = 64;   // plain mode: requests enqueued ahead
 constexpr size_t ALONE_QUEUE = 16;     // large_alone: batch beyond this many waiting
 constexpr size_t GROUP_MAX = 16;       // shuffles one rp_shuffle_group call takes
+// Resident mode: the kernel is stopped after this long without work (and
+// launched again when work arrives); on its own it leaves after 30 s with
+// nothing to claim; a gang that has not formed within 1 s is given back and
+// its request runs on one workgroup instead.
+constexpr uint64_t RES_IDLE_STOP_NS = 20000000;
+constexpr uint64_t RES_IDLE_TICKS = 3000000000ull;   // 100 MHz ticks
+constexpr uint64_t RES_FORM_TICKS = 100000000ull;
 
 uint64_t now_ns()
 {
@@ -137,6 +150,31 @@ struct Req {
     uint64_t rounds = 0;
     uint32_t aux_words = 0;
     bool large = false;
+    // resident mode
+    bool gang_ok = false;       // n >= 2^large_log2: may run on a gang
+    bool force_single = false;  // its gang could not form: one workgroup
+    uint64_t entry = 0;         // ring entry while posted
+    uint32_t gang = 1;
+    uint64_t aux_off = 0, aux_bytes = 0;
+    bool has_aux = false;
+};
+
+struct Resident {
+    rpres::Entry *ring = nullptr;       // pinned host memory
+    rpres::Result *res = nullptr;       // pinned host memory
+    uint32_t *stop = nullptr;           // pinned host memory
+    void *ctl = nullptr;                // device memory
+    hipStream_t stream = nullptr;       // this server's own
+    hipEvent_t ev = nullptr;            // recorded after each launch
+    bool running = false;
+    bool stop_sent = false;
+    uint32_t grid = 0;
+    uint64_t posted = 0;                // entries posted so far
+    std::vector<uint64_t> slot_ticket;  // ticket in each ring slot (0: free)
+    uint32_t busy_slots = 0;
+    uint32_t gangs_out = 0;             // posted gang entries not done yet
+    uint64_t idle_since = 0;
+    uint64_t form_ticks = RES_FORM_TICKS;
 };
 
 struct Launch {
@@ -175,6 +213,7 @@ struct Server {
     rp_server_stats stats{};
 
     std::vector<Launch> inflight;       // dispatcher thread only
+    Resident res;                       // resident mode
     std::thread thread;
     int thread_error = RP_OK;
 };
@@ -625,18 +664,269 @@ int launch_plain_one(Server &s)
     return RP_OK;
 }
 
+// ------------------------------------------------------------ resident mode
+
+// Fail every posted entry (the kernel or a device call failed); caller holds mu.
+void res_fail_posted(Server &s, int rc)
+{
+    Resident &R = s.res;
+    for (uint32_t slot = 0; slot < rpres::RING && R.busy_slots; slot++) {
+        const uint64_t t = R.slot_ticket[slot];
+        if (t == 0)
+            continue;
+        Req &r = s.reqs[t];
+        if (r.has_aux) {
+            s.arena.free(r.aux_off, r.aux_bytes);
+            r.has_aux = false;
+        }
+        R.slot_ticket[slot] = 0;
+        R.busy_slots--;
+        mark_done(s, t, rc);
+    }
+    R.gangs_out = 0;
+    s.thread_error = rc;
+}
+
+// The end of the kernel, and the results of finished ring entries.  An entry
+// whose gang could not form did not run: it is posted again, for one
+// workgroup.
+bool res_reap(Server &s)
+{
+    Resident &R = s.res;
+    bool progress = false;
+    if (R.running) {
+        const hipError_t e = hipEventQuery(R.ev);
+        if (e == hipSuccess) {
+            R.running = false;
+            R.stop_sent = false;
+            progress = true;
+        } else if (e != hipErrorNotReady) {
+            R.running = false;
+            std::lock_guard<std::mutex> lk(s.mu);
+            res_fail_posted(s, RP_EDEVICE);
+            return true;
+        }
+    }
+    if (R.busy_slots == 0)
+        return progress;
+    std::lock_guard<std::mutex> lk(s.mu);
+    for (uint32_t slot = 0; slot < rpres::RING && R.busy_slots; slot++) {
+        const uint64_t t = R.slot_ticket[slot];
+        if (t == 0)
+            continue;
+        Req &r = s.reqs[t];
+        if (__atomic_load_n(&R.res[slot].done, __ATOMIC_ACQUIRE) != r.entry + 1)
+            continue;
+        const int32_t status = R.res[slot].status;
+        R.slot_ticket[slot] = 0;
+        R.busy_slots--;
+        if (r.gang > 1)
+            R.gangs_out--;
+        if (r.has_aux) {
+            s.arena.free(r.aux_off, r.aux_bytes);
+            r.has_aux = false;
+        }
+        progress = true;
+        if (status == RP_PENDING) {
+            r.force_single = true;
+            r.state = RP_REQ_ADMITTED;
+            s.admitted[0].push_front(t);
+            continue;
+        }
+        r.rounds = R.res[slot].rounds;
+        mark_done(s, t, status);
+    }
+    s.stats.bytes_in_use = s.arena.in_use();
+    return progress;
+}
+
+// Post admitted requests, in admission order, to the ring.  A request of at
+// least 2^large_log2 elements runs on a gang when one can be planned: up to a
+// quarter of the kernel's workgroups, halved for every gang already posted
+// (under load, smaller gangs and then single workgroups keep the device's
+// throughput), and when the arena holds its tables.
+bool res_post(Server &s)
+{
+    Resident &R = s.res;
+    bool progress = false;
+    std::lock_guard<std::mutex> lk(s.mu);
+    while (!s.admitted[0].empty()) {
+        const uint32_t slot = (uint32_t)(R.posted & (rpres::RING - 1));
+        if (R.slot_ticket[slot] != 0)
+            break;   // the ring is full up to the oldest unfinished entry
+        const uint64_t t = s.admitted[0].front();
+        Req &r = s.reqs[t];
+        const uint32_t max_gang = (R.grid / 4) >> std::min<uint32_t>(R.gangs_out, 8);
+        const bool allow = r.gang_ok && !r.force_single && max_gang >= 8;
+        rpres::Entry e;
+        uint64_t auxb = 0;
+        int rc = rpint::resident_plan(r.q.n, r.q.elem_bytes, r.q.eps, max_gang, s.device, allow,
+                                      &e, &auxb);
+        if (rc == RP_OK && e.gang > 1) {
+            uint64_t off = 0;
+            if (s.arena.alloc(auxb, &off)) {
+                r.aux_off = off;
+                r.aux_bytes = auxb;
+                r.has_aux = true;
+            } else {
+                rc = rpint::resident_plan(r.q.n, r.q.elem_bytes, r.q.eps, 0, s.device, false, &e,
+                                          &auxb);
+            }
+        }
+        s.admitted[0].pop_front();
+        progress = true;
+        if (rc != RP_OK) {
+            mark_done(s, t, rc);
+            continue;
+        }
+        e.A = s.base + r.off;
+        e.aux = r.has_aux ? s.base + r.aux_off : nullptr;
+        e.seed = r.q.seed;
+        e.fill = r.q.init == RP_INIT_COPY ? rpres::FILL_COPY : rpres::FILL_IDENTITY;
+        e.src = r.q.src;
+        // the entry, then its sequence number
+        rpres::Entry *dst = &R.ring[slot];
+        std::memcpy(static_cast<void *>(dst), &e, offsetof(rpres::Entry, seq));
+        __atomic_store_n(&dst->seq, R.posted + 1, __ATOMIC_RELEASE);
+        r.entry = R.posted++;
+        r.gang = e.gang;
+        r.aux_words = e.aux_words;
+        r.state = RP_REQ_RUNNING;
+        r.t_launch = now_ns();
+        R.slot_ticket[slot] = t;
+        R.busy_slots++;
+        if (e.gang > 1)
+            R.gangs_out++;
+    }
+    s.stats.bytes_in_use = s.arena.in_use();
+    s.stats.peak_bytes = s.arena.peak();
+    return progress;
+}
+
+// Launch the kernel when entries wait and it is not running (it starts at the
+// oldest unfinished entry: everything a previous launch claimed has
+// finished); stop it after RES_IDLE_STOP_NS without work, or at once when
+// the server is being destroyed and nothing is left.
+bool res_manage(Server &s, bool stopping)
+{
+    Resident &R = s.res;
+    bool work;
+    uint64_t first = UINT64_MAX;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        work = R.busy_slots > 0 || !s.admitted[0].empty();
+        if (R.busy_slots > 0 && !R.running)
+            for (uint32_t slot = 0; slot < rpres::RING; slot++)
+                if (R.slot_ticket[slot] != 0)
+                    first = std::min(first, s.reqs[R.slot_ticket[slot]].entry);
+    }
+    if (first != UINT64_MAX) {
+        __atomic_store_n(R.stop, 0u, __ATOMIC_RELEASE);
+        const rpres::Launch L{R.ring, R.res, R.stop, R.ctl, first, RES_IDLE_TICKS,
+                              R.form_ticks, R.grid};
+        int rc = rpint::resident_launch(L, R.stream);
+        if (rc == RP_OK && hipEventRecord(R.ev, R.stream) != hipSuccess)
+            rc = RP_EDEVICE;
+        std::lock_guard<std::mutex> lk(s.mu);
+        if (rc != RP_OK) {
+            res_fail_posted(s, rc);
+            return true;
+        }
+        R.running = true;
+        R.stop_sent = false;
+        R.idle_since = 0;
+        s.stats.launches++;
+        return true;
+    }
+    if (R.running && !R.stop_sent) {
+        if (work) {
+            R.idle_since = 0;
+        } else {
+            const uint64_t t = now_ns();
+            if (R.idle_since == 0)
+                R.idle_since = t;
+            if (stopping || t - R.idle_since > RES_IDLE_STOP_NS) {
+                __atomic_store_n(R.stop, 1u, __ATOMIC_RELEASE);
+                R.stop_sent = true;
+            }
+        }
+    }
+    return false;
+}
+
+int res_create(Server &s)
+{
+    Resident &R = s.res;
+    R.slot_ticket.assign(rpres::RING, 0);
+    // RP_RES_FORM_US (environment) shortens the time a gang has to form, so
+    // that tests can make leaders give their requests back.
+    const char *fu = getenv("RP_RES_FORM_US");
+    if (fu && *fu)
+        R.form_ticks = (uint64_t)std::max(0, atoi(fu)) * 100;
+    if (rpint::resident_grid(s.device, &R.grid) != RP_OK)
+        return RP_EDEVICE;
+    if (hipHostMalloc(reinterpret_cast<void **>(&R.ring), sizeof(rpres::Entry) * rpres::RING,
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&R.res), sizeof(rpres::Result) * rpres::RING,
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&R.stop), 64, hipHostMallocCoherent) != hipSuccess)
+        return RP_ENOMEM;
+    std::memset(static_cast<void *>(R.ring), 0, sizeof(rpres::Entry) * rpres::RING);
+    std::memset(static_cast<void *>(R.res), 0, sizeof(rpres::Result) * rpres::RING);
+    *R.stop = 0;
+    if (hipMalloc(&R.ctl, rpint::resident_ctl_bytes()) != hipSuccess)
+        return RP_ENOMEM;
+    if (hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&R.ev, hipEventDisableTiming) != hipSuccess)
+        return RP_EDEVICE;
+    return RP_OK;
+}
+
+void res_destroy(Server &s)
+{
+    Resident &R = s.res;
+    if (R.stream) {
+        if (R.stop)
+            __atomic_store_n(R.stop, 1u, __ATOMIC_RELEASE);
+        (void)hipStreamSynchronize(R.stream);
+        (void)hipStreamDestroy(R.stream);
+    }
+    if (R.ev)
+        (void)hipEventDestroy(R.ev);
+    if (R.ctl)
+        (void)hipFree(R.ctl);
+    if (R.ring)
+        (void)hipHostFree(R.ring);
+    if (R.res)
+        (void)hipHostFree(R.res);
+    if (R.stop)
+        (void)hipHostFree(R.stop);
+    R = Resident{};
+}
+
 void dispatcher(Server *sp)
 {
     Server &s = *sp;
     (void)hipSetDevice(s.device);
     const auto tick = std::chrono::microseconds(s.cfg.tick_us ? s.cfg.tick_us : 50);
+    const bool resident = s.cfg.mode == RP_SERVE_RESIDENT;
     for (;;) {
         bool progress = reap(s);
+        if (resident)
+            progress = res_reap(s) || progress;
         {
             std::lock_guard<std::mutex> lk(s.mu);
             progress = admit(s) || progress;
         }
-        if (s.cfg.mode == RP_SERVE_PLAIN) {
+        if (resident) {
+            progress = res_post(s) || progress;
+            bool stopping;
+            {
+                std::lock_guard<std::mutex> lk(s.mu);
+                stopping = s.stopping;
+            }
+            progress = res_manage(s, stopping) || progress;
+        } else if (s.cfg.mode == RP_SERVE_PLAIN) {
             // keep up to PLAIN_AHEAD requests enqueued on the single stream
             while (s.inflight.size() < PLAIN_AHEAD) {
                 const int rc = launch_plain_one(s);
@@ -679,7 +969,7 @@ void dispatcher(Server *sp)
                     mark_done(s, t, RP_ECANCELED);
                 s.admitted[c].clear();
             }
-            if (s.inflight.empty())
+            if (s.inflight.empty() && s.res.busy_slots == 0 && !s.res.running)
                 break;
         }
         if (s.thread_error != RP_OK && s.inflight.empty()) {
@@ -692,7 +982,7 @@ void dispatcher(Server *sp)
                 s.admitted[c].clear();
             }
             s.queue.clear();
-            if (s.stopping)
+            if (s.stopping && !s.res.running)
                 break;
         }
         if (!progress)
@@ -730,6 +1020,7 @@ int server_streams(int device, hipStream_t *out)
 
 void destroy_server(Server *s)
 {
+    res_destroy(*s);
     for (int i = 0; i < N_STREAMS; i++) {
         if (s->streams[i])
             (void)hipStreamSynchronize(s->streams[i]);   // shared: not destroyed
@@ -759,7 +1050,9 @@ int rp_set_mem_budget(uint64_t bytes)
 int rp_server_create(const rp_server_config *cfg, uint64_t *server)
 {
     if (cfg == nullptr || server == nullptr ||
-        (cfg->mode != RP_SERVE_BATCHED && cfg->mode != RP_SERVE_PLAIN) || cfg->large_log2 > 40)
+        (cfg->mode != RP_SERVE_BATCHED && cfg->mode != RP_SERVE_PLAIN &&
+         cfg->mode != RP_SERVE_RESIDENT) ||
+        cfg->large_log2 > 40)
         return RP_EINVAL;
     Server *s = new Server;
     s->cfg = *cfg;
@@ -788,6 +1081,13 @@ int rp_server_create(const rp_server_config *cfg, uint64_t *server)
         destroy_server(s);
         return RP_EDEVICE;
     }
+    if (s->cfg.mode == RP_SERVE_RESIDENT) {
+        const int rc = res_create(*s);
+        if (rc != RP_OK) {
+            destroy_server(s);
+            return rc;
+        }
+    }
     s->thread = std::thread(dispatcher, s);
     std::lock_guard<std::mutex> lk(g_smu);
     *server = g_next_server++;
@@ -803,6 +1103,18 @@ int rp_server_submit(uint64_t server, const rp_server_request *req, uint64_t *ti
     const uint64_t bytes = req->n * req->elem_bytes;
     if (rpserve::Arena::rounded(bytes) > s->arena.size())
         return RP_EINVAL;
+    if (s->cfg.mode == RP_SERVE_RESIDENT && req->init == RP_INIT_COPY) {
+        // The kernel reads the source itself: it must be device memory or
+        // pinned host memory.
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, req->src) != hipSuccess) {
+            (void)hipGetLastError();
+            return RP_EINVAL;
+        }
+        if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeHost &&
+            at.type != hipMemoryTypeManaged)
+            return RP_EINVAL;
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping)
@@ -811,7 +1123,8 @@ int rp_server_submit(uint64_t server, const rp_server_request *req, uint64_t *ti
         Req &r = s->reqs[t];
         r.q = *req;
         r.bytes = bytes;
-        r.large = req->n >= (1ull << s->cfg.large_log2);
+        r.gang_ok = req->n >= (1ull << s->cfg.large_log2);
+        r.large = r.gang_ok && s->cfg.mode != RP_SERVE_RESIDENT;
         r.t_submit = now_ns();
         s->queue.push_back(t);
         s->stats.submitted++;
