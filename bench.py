@@ -14,8 +14,11 @@ CPU oracle (sampled positions, exact) and for being a permutation.
 `--workload serve` replays Poisson arrival traces (exponential gaps, seed 7)
 at each rate for --duration seconds, n = floor(2^U) with U ~ Uniform[10, 26)
 from a SplitMix64 stream (seed 7), int64 A[i] = i, request seed 10^6 + id,
-eps = 0.5, through a server with a 64 GiB arena, once batched and once with
-one plain launch per request; it reports elements/s and p50/p99 latency.
+eps = 0.5, through a server with a 64 GiB arena: resident (one kernel takes
+each request as it arrives; large requests, n >= 2^22, on gangs of
+workgroups), batched (launches of every admitted request; large ones in group
+launches), and one plain launch per request; it reports elements/s and
+p50/p99 latency.
 
 `--workload ablation` times the reservation variants (final, one reservation
 without the dense window, Algorithm 1's two reservations, the non-in-place
@@ -146,6 +149,8 @@ def main():
     ap.add_argument("--rates", default="50,200,1000",
                     help="serve workload: arrival rates (requests/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-modes", default="resident,batched,plain",
+                    help="serving modes to replay (resident, batched, plain)")
     ap.add_argument("--serve-rate", type=float, default=200.0,
                     help="plain workload: arrival rate of the short served leg")
     ap.add_argument("--serve-duration", type=float, default=8.0,
@@ -224,10 +229,22 @@ def reference_copy(rp, stream, log, nbytes=COPY_BYTES):
     return ms
 
 
-def serve_leg(rp, rate, duration, log):
-    """A short served run at one Poisson rate, batched server against one
-    plain launch per request, on the same trace (the serving workload's
-    request mix)."""
+SERVE_MODES = (("resident", "RP_SERVE_RESIDENT"), ("batched", "RP_SERVE_BATCHED"),
+               ("plain", "RP_SERVE_PLAIN"))
+
+
+def _serve_modes(names):
+    want = [m.strip() for m in names.split(",") if m.strip()]
+    bad = [m for m in want if m not in dict(SERVE_MODES)]
+    if bad or not want:
+        raise SystemExit(f"unknown serving mode(s) {bad}; choose from {[m for m, _ in SERVE_MODES]}")
+    return [(m, c) for m, c in SERVE_MODES if m in want]
+
+
+def serve_leg(rp, rate, duration, log, args_modes="resident,batched,plain"):
+    """A short served run at one Poisson rate through the resident server,
+    the batched server and one plain launch per request, on the same trace
+    (the serving workload's request mix)."""
     import numpy as np
     from paper_2103_01216_amd import workloads
     count = max(1, int(rate * duration))
@@ -238,14 +255,17 @@ def serve_leg(rp, rate, duration, log):
     rec = {"rate_per_s": rate, "duration_s": duration, "requests": count,
            "offered_elements_per_s": float(sizes.sum()) / float(arrivals[-1]),
            "request_sizes": "n=floor(2^U), U~Uniform[10,26), int64, eps=0.5"}
-    for name, mode in (("batched", rp.RP_SERVE_BATCHED), ("plain", rp.RP_SERVE_PLAIN)):
-        lats, elems, span, unfinished, st = _replay(rp, mode, arrivals, sizes, seeds, log,
-                                                    drain_s=duration)
+    for name, const in _serve_modes(args_modes):
+        mode = getattr(rp, const)
+        lats, elems, span, unfinished, st, detail = _replay(rp, mode, arrivals, sizes, seeds,
+                                                            log, drain_s=duration)
         lat_ms = np.array(lats) * 1e3
         rec[name] = {"elements_per_s": elems / span,
                      "p50_ms": float(np.percentile(lat_ms, 50)),
                      "p99_ms": float(np.percentile(lat_ms, 99)),
                      "completed": count - unfinished, "unfinished": unfinished}
+        if detail:
+            rec[name].update(detail)
         log(f"served {rate:g}/s {name}: {elems / span:.3g} elements/s, "
             f"p50 {rec[name]['p50_ms']:.2f} ms, p99 {rec[name]['p99_ms']:.2f} ms, "
             f"unfinished {unfinished}")
@@ -328,7 +348,7 @@ def run_plain(args, log):
 
     served = None
     if args.serve_duration > 0:
-        served = serve_leg(rp, args.serve_rate, args.serve_duration, log)
+        served = serve_leg(rp, args.serve_rate, args.serve_duration, log, args.serve_modes)
 
     alg_bytes = 4 * eb * n                      # A[s], A[H[s]]: read + write
     achieved = alg_bytes / (ms * 1e-3) / 1e9    # GB/s over the kernel's time
@@ -600,12 +620,15 @@ def run_batch(args, log):
 
 SERVE = {"lo_log2": 10, "hi_log2": 26, "size_seed": 7, "arrival_seed": 7,
          "seed_base": 10**6, "eps": 0.5, "budget": 64 << 30, "elem_bytes": 8}
+SERVE_LARGE = 1 << 22   # the servers' large-request threshold (large_log2 = 22)
 
 
 def _replay(rp, mode, arrivals, sizes, seeds, log, drain_s):
     """Submit each request at its arrival time; collect completion times.
-    Returns (latencies_s, completed_elements, span_s, unfinished)."""
+    Returns (latencies_s, completed_elements, span_s, unfinished, server
+    stats, large-request detail)."""
     import threading
+    import numpy as np
     srv = rp.Server(SERVE["budget"], mode=mode, auto_release=True,
                     large_alone=(mode == rp.RP_SERVE_BATCHED))
     tickets = {}
@@ -654,9 +677,24 @@ def _replay(rp, mode, arrivals, sizes, seeds, log, drain_s):
         else:
             lats.append((now_ns - srv.info(t)["t_submit_ns"]) * 1e-9)
     elems = sum(int(sizes[tickets[t]]) for t in done)
+    # requests of at least 2^22 elements (gangs or group launches): their
+    # latency percentiles, and in resident mode how many ran on one workgroup
+    big = [(done[t][0], done[t][1]["workgroups"]) for t in done
+           if int(sizes[tickets[t]]) >= SERVE_LARGE]
+    detail = None
+    if big:
+        bl = np.array([b[0] for b in big]) * 1e3
+        detail = {"large_requests": len(big), "large_p50_ms": float(np.percentile(bl, 50)),
+                  "large_p99_ms": float(np.percentile(bl, 99)),
+                  "large_on_one_workgroup": sum(1 for b in big if b[1] == 1)}
+        small = [done[t][0] for t in done if int(sizes[tickets[t]]) < SERVE_LARGE]
+        if small:
+            sl = np.array(small) * 1e3
+            detail["small_p50_ms"] = float(np.percentile(sl, 50))
+            detail["small_p99_ms"] = float(np.percentile(sl, 99))
     srv.close()
     span = max((t_last - t_first) * 1e-9, 1e-9)
-    return lats, elems, span, unfinished, st
+    return lats, elems, span, unfinished, st, detail
 
 
 def run_serve(args, log):
@@ -679,23 +717,27 @@ def run_serve(args, log):
         seeds = [SERVE["seed_base"] + i for i in range(count)]
         offered = float(sizes.sum()) / float(arrivals[-1])
         rec = {"requests": count, "offered_elements_per_s": offered}
-        for name, mode in (("batched", rp.RP_SERVE_BATCHED), ("plain", rp.RP_SERVE_PLAIN)):
+        for name, const in _serve_modes(args.serve_modes):
+            mode = getattr(rp, const)
             log(f"rate {lam:g}/s, {name}: {count} requests, offered {offered:.3g} elements/s")
-            lats, elems, span, unfinished, st = _replay(rp, mode, arrivals, sizes, seeds, log,
-                                                        drain_s=max(30.0, args.duration / 2))
+            lats, elems, span, unfinished, st, detail = _replay(
+                rp, mode, arrivals, sizes, seeds, log, drain_s=max(30.0, args.duration / 2))
             lat_ms = np.array(lats) * 1e3
             rec[name] = {"elements_per_s": elems / span,
                          "p50_ms": float(np.percentile(lat_ms, 50)),
                          "p99_ms": float(np.percentile(lat_ms, 99)),
                          "completed": count - unfinished, "unfinished": unfinished,
                          "launches": st["launches"], "peak_bytes": st["peak_bytes"]}
+            if detail:
+                rec[name].update(detail)
             log(f"  {name}: {elems / span:.3g} elements/s, p50 {rec[name]['p50_ms']:.2f} ms, "
-                f"p99 {rec[name]['p99_ms']:.2f} ms, launches {st['launches']}")
+                f"p99 {rec[name]['p99_ms']:.2f} ms, launches {st['launches']}; {detail}")
         per_rate[f"{lam:g}"] = rec
     top = per_rate[f"{rates[-1]:g}"]
+    first_mode = _serve_modes(args.serve_modes)[0][0]
     out = {
         "metric": "served shuffle elements/s with p50/p99 latency (Poisson arrivals)",
-        "value": top["batched"]["elements_per_s"],
+        "value": top[first_mode]["elements_per_s"],
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": len(rates),
@@ -710,7 +752,7 @@ def run_serve(args, log):
                                "U~Uniform[10,26) from SplitMix64 stream seed 7, int64 "
                                "A[i]=i, seed 1e6+id, eps=0.5, 64 GiB arena",
                    "duration_s": args.duration, "rates": per_rate,
-                   "value_is": f"batched elements/s at {rates[-1]:g} requests/s"},
+                   "value_is": f"{first_mode} elements/s at {rates[-1]:g} requests/s"},
     }
     print(json.dumps(out), flush=True)
 

@@ -548,7 +548,8 @@ typedef struct rp_server_ticket_info {
                                     after release) */
     uint64_t rounds;             /* rounds run (batched and resident modes) */
     uint32_t aux_words;          /* round-state words used */
-    uint32_t reserved;
+    uint32_t workgroups;         /* resident mode: workgroups it ran on (1,
+                                    or its gang's size); 0 in other modes */
 } rp_server_ticket_info;
 
 typedef struct rp_server_stats {

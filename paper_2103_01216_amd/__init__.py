@@ -543,7 +543,7 @@ class rp_server_ticket_info(ctypes.Structure):
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
                 ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
                 ("A", ctypes.c_void_p), ("rounds", ctypes.c_uint64),
-                ("aux_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("aux_words", ctypes.c_uint32), ("workgroups", ctypes.c_uint32)]
 
 
 class rp_server_stats(ctypes.Structure):
@@ -630,8 +630,7 @@ class Server:
         rc = _server_lib().rp_server_info(self.handle, ticket, ctypes.byref(out))
         if rc != RP_OK:
             raise RpError(rc, "rp_server_info")
-        return {f: getattr(out, f) for f, _ in rp_server_ticket_info._fields_
-                if f != "reserved"}
+        return {f: getattr(out, f) for f, _ in rp_server_ticket_info._fields_}
 
     def completed(self, max_count: int = 4096) -> list:
         buf = (ctypes.c_uint64 * max_count)()

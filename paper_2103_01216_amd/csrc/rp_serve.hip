@@ -172,9 +172,10 @@ struct Resident {
     uint64_t posted = 0;                // entries posted so far
     std::vector<uint64_t> slot_ticket;  // ticket in each ring slot (0: free)
     uint32_t busy_slots = 0;
-    uint32_t gangs_out = 0;             // posted gang entries not done yet
+    uint32_t wgs_out = 0;               // workgroups of the posted entries not done yet
     uint64_t idle_since = 0;
     uint64_t form_ticks = RES_FORM_TICKS;
+    uint32_t gang_cap = 0;              // largest gang (0: a quarter of the grid)
 };
 
 struct Launch {
@@ -683,7 +684,7 @@ void res_fail_posted(Server &s, int rc)
         R.busy_slots--;
         mark_done(s, t, rc);
     }
-    R.gangs_out = 0;
+    R.wgs_out = 0;
     s.thread_error = rc;
 }
 
@@ -720,8 +721,7 @@ bool res_reap(Server &s)
         const int32_t status = R.res[slot].status;
         R.slot_ticket[slot] = 0;
         R.busy_slots--;
-        if (r.gang > 1)
-            R.gangs_out--;
+        R.wgs_out -= std::min(R.wgs_out, r.gang);
         if (r.has_aux) {
             s.arena.free(r.aux_off, r.aux_bytes);
             r.has_aux = false;
@@ -742,9 +742,11 @@ bool res_reap(Server &s)
 
 // Post admitted requests, in admission order, to the ring.  A request of at
 // least 2^large_log2 elements runs on a gang when one can be planned: up to a
-// quarter of the kernel's workgroups, halved for every gang already posted
-// (under load, smaller gangs and then single workgroups keep the device's
-// throughput), and when the arena holds its tables.
+// quarter of the kernel's workgroups and half of those the posted requests do
+// not hold, at least 8 (under load gangs shrink: a small gang's rounds cost
+// more workgroup time per swap than a large one's, but far less than one
+// workgroup's), and when the arena holds its tables; otherwise on one
+// workgroup.
 bool res_post(Server &s)
 {
     Resident &R = s.res;
@@ -756,7 +758,9 @@ bool res_post(Server &s)
             break;   // the ring is full up to the oldest unfinished entry
         const uint64_t t = s.admitted[0].front();
         Req &r = s.reqs[t];
-        const uint32_t max_gang = (R.grid / 4) >> std::min<uint32_t>(R.gangs_out, 8);
+        const uint32_t free_wgs = R.grid - std::min(R.grid, R.wgs_out);
+        const uint32_t max_gang = std::min({R.grid / 4, free_wgs / 2,
+                                            R.gang_cap ? R.gang_cap : R.grid});
         const bool allow = r.gang_ok && !r.force_single && max_gang >= 8;
         rpres::Entry e;
         uint64_t auxb = 0;
@@ -795,8 +799,7 @@ bool res_post(Server &s)
         r.t_launch = now_ns();
         R.slot_ticket[slot] = t;
         R.busy_slots++;
-        if (e.gang > 1)
-            R.gangs_out++;
+        R.wgs_out += e.gang;
     }
     s.stats.bytes_in_use = s.arena.in_use();
     s.stats.peak_bytes = s.arena.peak();
@@ -863,6 +866,11 @@ int res_create(Server &s)
     const char *fu = getenv("RP_RES_FORM_US");
     if (fu && *fu)
         R.form_ticks = (uint64_t)std::max(0, atoi(fu)) * 100;
+    // RP_RES_MAX_GANG (environment) caps the gang size (a tuning override;
+    // below 8 every request runs on one workgroup).
+    const char *mg = getenv("RP_RES_MAX_GANG");
+    if (mg && *mg)
+        R.gang_cap = (uint32_t)std::max(1, atoi(mg));
     if (rpint::resident_grid(s.device, &R.grid) != RP_OK)
         return RP_EDEVICE;
     if (hipHostMalloc(reinterpret_cast<void **>(&R.ring), sizeof(rpres::Entry) * rpres::RING,
@@ -1154,6 +1162,7 @@ int rp_server_info(uint64_t server, uint64_t ticket, rp_server_ticket_info *info
     info->A = r.has_mem ? static_cast<void *>(s->base + r.off) : nullptr;
     info->rounds = r.rounds;
     info->aux_words = r.aux_words;
+    info->workgroups = s->cfg.mode == RP_SERVE_RESIDENT ? r.gang : 0;
     return RP_OK;
 }
 
