@@ -935,6 +935,7 @@ __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
 constexpr uint32_t RES_WG = WG1;          // the one-barrier body's workgroup
 using ResShape = rpwg::Shape<RES_WG>;
 constexpr uint32_t RES_MASK = rpres::RING - 1;
+constexpr int RES_IDLE_SLEEP = 32;        // idle poll interval, in units of 64 clocks
 
 struct ResCtl {
     uint64_t head;          // next entry to claim
@@ -1085,7 +1086,7 @@ __device__ __forceinline__ uint32_t res_next(const ResParams &P, uint64_t *entry
             (void)xchg_agent(&c->exitf, 1u);
             return RCMD_EXIT;
         }
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(RES_IDLE_SLEEP);
     }
 }
 

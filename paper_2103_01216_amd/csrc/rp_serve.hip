@@ -759,8 +759,7 @@ bool res_post(Server &s)
         const uint64_t t = s.admitted[0].front();
         Req &r = s.reqs[t];
         const uint32_t free_wgs = R.grid - std::min(R.grid, R.wgs_out);
-        const uint32_t max_gang = std::min({R.grid / 4, free_wgs / 2,
-                                            R.gang_cap ? R.gang_cap : R.grid});
+        const uint32_t max_gang = std::min(free_wgs / 2, R.gang_cap ? R.gang_cap : R.grid / 4);
         const bool allow = r.gang_ok && !r.force_single && max_gang >= 8;
         rpres::Entry e;
         uint64_t auxb = 0;
@@ -866,8 +865,9 @@ int res_create(Server &s)
     const char *fu = getenv("RP_RES_FORM_US");
     if (fu && *fu)
         R.form_ticks = (uint64_t)std::max(0, atoi(fu)) * 100;
-    // RP_RES_MAX_GANG (environment) caps the gang size (a tuning override;
-    // below 8 every request runs on one workgroup).
+    // RP_RES_MAX_GANG (environment) replaces the largest gang, a quarter of
+    // the grid (a tuning override; below 8 every request runs on one
+    // workgroup).
     const char *mg = getenv("RP_RES_MAX_GANG");
     if (mg && *mg)
         R.gang_cap = (uint32_t)std::max(1, atoi(mg));
