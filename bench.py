@@ -21,10 +21,14 @@ launches), and one plain launch per request; it reports elements/s and
 p50/p99 latency.
 
 `--workload ablation` times the reservation variants (final, one reservation
-without the dense window, Algorithm 1's two reservations, the non-in-place
-linear array) on the n = 2^30 int64 workload, each checked byte-equal to the
-final variant's result, and sweeps the auxiliary bound at n = 10^8 int64 (the
-paper's aux-space table: 0.4 %, 1 %, 2 %, 4 % of n, plus smaller bounds).
+without the dense window, Algorithm 1's two reservations with H of the active
+swaps in registers, in a prefix-sized array (flat) or in a hashed table
+(naive), the non-in-place linear array) on the n = 2^30 int64 workload, each
+checked byte-equal to the final variant's result, and sweeps the auxiliary
+bound at n = 10^8 int64 (the paper's aux-space table: 0.4 %, 1 %, 2 %, 4 % of
+n, plus smaller bounds).  With --variants-once it only runs each variant once
+(seed 1, after one rp_shuffle_inplace call as the reference), the launches a
+counter profile attributes in that order.
 
 `--workload list` ranks one random list of n = 10^8 elements (two 64-bit
 pointer words each, the paper's list-contraction inputs) by in-place list
@@ -149,6 +153,8 @@ def main():
     ap.add_argument("--rates", default="50,200,1000",
                     help="serve workload: arrival rates (requests/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants-once", action="store_true",
+                    help="ablation workload: one launch per variant, no timing or sweep")
     ap.add_argument("--serve-modes", default="resident,batched,plain",
                     help="serving modes to replay (resident, batched, plain)")
     ap.add_argument("--serve-rate", type=float, default=200.0,
@@ -785,7 +791,20 @@ def run_ablation(args, log):
     ref = torch.arange(n, dtype=torch.int64, device=dev)
     rp.rp_shuffle_inplace(ref, seed=WORKLOAD["seed"], eps=0.5, stream=stream, stats=False)
     variants = {}
-    for name in ("final", "oneres", "twores", "linear"):
+    names = ("final", "oneres", "twores", "flat", "naive", "linear")
+    if args.variants_once:
+        for name in names:
+            A.copy_(torch.arange(n, dtype=torch.int64, device=dev))
+            st = rp.rp_shuffle_variant(A, variant=name, seed=WORKLOAD["seed"], eps=0.5,
+                                       stream=stream).get()
+            same = bool(torch.equal(A, ref))
+            log(f"n=2^30 {name}: rounds {st['rounds']}, attempts {st['attempts']}, "
+                f"k {st['k']}, aux {st['aux_words']} words, equal to final: {same}")
+            if not same:
+                log("PARITY FAILURE")
+                sys.exit(1)
+        return
+    for name in names:
         A.copy_(torch.arange(n, dtype=torch.int64, device=dev))
         rp.rp_shuffle_variant(A, variant=name, seed=WORKLOAD["seed"], eps=0.5,
                               stream=stream, stats=False)

@@ -173,7 +173,15 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
  *                      through the hashed slots (no dense window)
  *   RP_VARIANT_TWORES  Algorithm 1 as printed: reservations on both s and
  *                      H[s] (hashed); a swap commits when both hold its own
- *                      priority
+ *                      priority; H[s] of every active swap held in registers
+ *   RP_VARIANT_FLAT    as RP_VARIANT_TWORES, with H[s] of the active swaps in
+ *                      an array of the prefix's size (one word per swap slot,
+ *                      written when the swap enters, read back to reserve and
+ *                      to commit)
+ *   RP_VARIANT_NAIVE   as RP_VARIANT_TWORES, with H[s] of the active swaps in
+ *                      a hashed table keyed by s (open addressing, twice the
+ *                      prefix's size, two parities cleared whole in turn):
+ *                      set every round, read back to commit
  *   RP_VARIANT_LINEAR  the non-in-place scheme: R is an array of n 8-byte
  *                      words (exact, never cleaned: the round number is part
  *                      of every priority) and k is the largest the grid
@@ -186,6 +194,8 @@ int rp_shuffle_inplace(void *A, uint64_t n, uint32_t elem_bytes,
 #define RP_VARIANT_ONERES 1
 #define RP_VARIANT_TWORES 2
 #define RP_VARIANT_LINEAR 3
+#define RP_VARIANT_FLAT 4
+#define RP_VARIANT_NAIVE 5
 
 int rp_shuffle_variant(void *A, uint64_t n, uint32_t elem_bytes,
                        const uint64_t *H, uint64_t seed, double eps, int variant,
@@ -340,7 +350,16 @@ typedef struct rp_batch_schedule {
  * requests): times trial launches of candidate schedules on scratch copies of
  * an evenly spaced sample of the requests (seed mode; the caller's arrays are
  * not touched), waits for them, writes the fastest to *out (host) and makes it
- * the default of later rp_batch_submit calls that pass no schedule.
+ * the default of later rp_batch_submit calls that pass no schedule.  The
+ * choice is remembered in a text file with the device (architecture and
+ * compute units), the record size, the eps values and the sample's size mix
+ * (share of requests per octave of n); a later call on the same kind of
+ * device, for the same record size and eps values and a size mix whose
+ * cumulative shares over the octaves stay within 0.15 of a remembered one
+ * (batches drawn from one distribution), takes the closest remembered
+ * schedule without trial runs.  The file is $RP_TUNE_CACHE, or
+ * $HOME/.cache/librp/batch_schedules.txt; RP_TUNE_CACHE set to the empty
+ * string turns this off.  A file that cannot be read or written is ignored.
  * Returns RP_OK, RP_EINVAL, RP_ENOMEM.
  */
 int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream,
@@ -474,7 +493,8 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
  * requests from a ring in host memory as they arrive, so a request starts on
  * the next free workgroup instead of with the next launch (admission at the
  * granularity of a workgroup's request boundary).  A request below
- * 2^large_log2 elements runs on one workgroup with its round state in LDS;
+ * 2^large_log2 elements (2^20 by default) runs on one workgroup with its
+ * round state in LDS;
  * a larger one on a gang of idle workgroups (up to a quarter of them, fewer
  * while other gangs are posted) that runs the one-barrier rounds with its
  * tables in the arena, counted against the admission budget and the
@@ -510,7 +530,7 @@ typedef struct rp_server_config {
     uint32_t max_batch;          /* requests per launch; 0: no limit */
     uint32_t large_log2;         /* n >= 2^large_log2 uses the large-request
                                     streams (resident mode: may run on a
-                                    gang); 0: 22 */
+                                    gang); 0: 22 (resident mode: 20) */
     uint32_t tick_us;            /* dispatcher poll interval; 0: 50 */
     uint32_t auto_release;       /* 1: free each array as soon as it is done
                                     (results are not kept) */

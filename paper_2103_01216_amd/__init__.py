@@ -151,8 +151,11 @@ RP_VARIANT_FINAL = 0
 RP_VARIANT_ONERES = 1
 RP_VARIANT_TWORES = 2
 RP_VARIANT_LINEAR = 3
+RP_VARIANT_FLAT = 4
+RP_VARIANT_NAIVE = 5
 VARIANTS = {"final": RP_VARIANT_FINAL, "oneres": RP_VARIANT_ONERES,
-            "twores": RP_VARIANT_TWORES, "linear": RP_VARIANT_LINEAR}
+            "twores": RP_VARIANT_TWORES, "linear": RP_VARIANT_LINEAR,
+            "flat": RP_VARIANT_FLAT, "naive": RP_VARIANT_NAIVE}
 
 
 def rp_shuffle_inplace(A, *, H=None, seed: int = 0, eps: float = 0.5,

@@ -119,6 +119,9 @@ struct Params {
     uint32_t variant;    // RP_VARIANT_*: how reservations are held and checked
     uint32_t lds_tab;    // 1: the launch uses the LDS variant of the kernel
     uint64_t *R64;       // RP_VARIANT_LINEAR: one priority word per position
+    uint32_t *hflat;     // RP_VARIANT_FLAT: H of each active swap, by swap slot
+    uint64_t *htab;      // RP_VARIANT_NAIVE: hashed (source + 1, H) pairs, two parities
+    uint32_t hcap;       // RP_VARIANT_NAIVE: entries per parity (a power of two)
     uint32_t wg_first;   // this shuffle's workgroups: [wg_first, wg_first + wg_count)
     uint32_t wg_count;   // of the launch (all of it, except in a group launch)
     uint32_t chunk_log2; // one-barrier kernel: fresh indices are dealt in chunks of 2^this
@@ -218,11 +221,52 @@ __device__ __forceinline__ bool plain_barrier(const Params &p, uint32_t w, uint3
     return sh_res[3] == 0;
 }
 
-// The rounds of one shuffle on its workgroups.  M: swap slots per lane.  EB:
+// The naive variant's table of H: open addressing with linear probing over
+// `cap` 64-bit entries (source + 1) << 32 | H, 0 = empty; at most half full.
+__device__ __forceinline__ uint32_t htab_home(uint32_t key, uint32_t cap)
+{
+    return (uint32_t)(((uint64_t)key * 0xD6E8FEB86659FD93ull) >> 32) & (cap - 1u);
+}
+
+__device__ __forceinline__ void htab_insert(uint64_t *tab, uint32_t cap, uint32_t key,
+                                            uint32_t val)
+{
+    const uint64_t e = ((uint64_t)(key + 1u) << 32) | val;
+    uint32_t i = htab_home(key, cap);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        uint64_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(&tab[i], &expect, e, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        i = (i + 1u) & (cap - 1u);
+    }
+}
+
+// H of `key`, or sets *missing when the key is absent (never, in a correct
+// round: every active swap inserted its pair in this round's parity).
+__device__ __forceinline__ uint32_t htab_find(const uint64_t *tab, uint32_t cap, uint32_t key,
+                                              bool *missing)
+{
+    uint32_t i = htab_home(key, cap);
+    for (uint32_t probe = 0; probe < cap; probe++) {
+        const uint64_t e = ld(&tab[i]);
+        if ((uint32_t)(e >> 32) == key + 1u)
+            return (uint32_t)e;
+        if (e == 0)
+            break;
+        i = (i + 1u) & (cap - 1u);
+    }
+    *missing = true;
+    return 0;
+}
+
+// The rounds of one shuffle on its workgroups.  HX: the flat and naive
+// variants (H of the active swaps outside the registers) are compiled in.
+// M: swap slots per lane.  EB:
 // record size held in registers (4, 8, 16), or 0 for any multiple of 4 up to
 // 256 bytes, moved after the decision.  LDS: a one-workgroup launch whose
 // slot array and window live in dynamic LDS.
-template <int M, int EB, bool LDS>
+template <int M, int EB, bool LDS, bool HX = false>
 __device__ __forceinline__ void rounds_body(const Params &p)
 {
     __shared__ uint32_t sh_wave[WAVES];
@@ -236,7 +280,13 @@ __device__ __forceinline__ void rounds_body(const Params &p)
     // reserves sources there, the linear one has exact per-position words.
     const uint32_t W = p.variant == RP_VARIANT_FINAL ? p.bmw * 32u : 0u;
     const bool linear = p.variant == RP_VARIANT_LINEAR;
-    const bool twores = p.variant == RP_VARIANT_TWORES;
+    // Algorithm 1's two reservations: the two-reservation variant holds H of
+    // every active swap in registers, the flat one in a prefix-sized array
+    // indexed by the swap's slot, the naive one in a hashed table keyed by
+    // the source.
+    const bool flat = HX && p.variant == RP_VARIANT_FLAT;
+    const bool naive = HX && p.variant == RP_VARIANT_NAIVE;
+    const bool twores = p.variant == RP_VARIANT_TWORES || flat || naive;
 
     // A one-workgroup launch keeps its slot array and window in LDS (the
     // same words, on chip): its rounds are then workgroup barriers and LDS
@@ -376,16 +426,36 @@ __device__ __forceinline__ void rounds_body(const Params &p)
                     } else {
                         src[m] = s;
                         tgt[m] = h;
+                        if (flat)
+                            st(&p.hflat[(uint64_t)m * G * WG + (uint64_t)w * WG + t], h);
                     }
                 }
             }
         }
-        // ---- 3. reserve: clean the stale window parity; priority write on
-        // the slot(s) of H[s]; dense window bit
+        // ---- 3. reserve: clean the stale window parity (and the naive
+        // table's stale parity, whose last lookups were before the gather);
+        // priority write on the slot(s) of H[s]; dense window bit
         {
             const uint32_t op = par ^ 1u;
             for (uint32_t i = w + G * t; i < p.bmw; i += G * WG)
                 clear_rmw(&bm[(uint64_t)op * p.bmw + i]);
+            if (naive)
+                for (uint32_t i = w + G * t; i < p.hcap; i += G * WG)
+                    (void)__hip_atomic_exchange(&p.htab[(uint64_t)op * p.hcap + i], (uint64_t)0,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // H of every active swap for this round's reservations: read back
+        // from the flat array, or (naive) set in this round's table.
+        if (flat || naive) {
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (src[m] == EMPTY)
+                    continue;
+                if (flat)
+                    tgt[m] = ld(&p.hflat[(uint64_t)m * G * WG + (uint64_t)w * WG + t]);
+                else
+                    htab_insert(p.htab + (uint64_t)par * p.hcap, p.hcap, src[m], tgt[m]);
+            }
         }
         uint32_t act = 0;
 #pragma unroll
@@ -474,7 +544,25 @@ __device__ __forceinline__ void rounds_body(const Params &p)
             break;
         }
 
-        // ---- 5. commit test and swap: issue every load, then decide
+        // ---- 5. commit test and swap: issue every load, then decide.  The
+        // flat and naive variants read H back first (array, or table).
+        if (flat || naive) {
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (src[m] == EMPTY)
+                    continue;
+                bool missing = false;
+                tgt[m] = flat ? ld(&p.hflat[(uint64_t)m * G * WG + (uint64_t)w * WG + t])
+                              : htab_find(p.htab + (uint64_t)par * p.hcap, p.hcap, src[m],
+                                          &missing);
+                if (missing) {
+                    // Cannot happen in a correct round; keep the result
+                    // right and report it in the status.
+                    tgt[m] = target_of(p, src[m]);
+                    st(&p.dstats[S_STATUS], (uint64_t)(int64_t)RP_EDEVICE);
+                }
+            }
+        }
         uint32_t t1[M], t2[M], q1[M], q2[M];
 #pragma unroll
         for (int m = 0; m < M; m++) {
@@ -562,10 +650,10 @@ __device__ __forceinline__ void rounds_body(const Params &p)
     }
 }
 
-template <int M, int EB, bool LDS>
+template <int M, int EB, bool LDS, bool HX = false>
 __global__ __launch_bounds__(WG) void rp_rounds_kernel(Params p)
 {
-    rounds_body<M, EB, LDS>(p);
+    rounds_body<M, EB, LDS, HX>(p);
 }
 
 // ------------------------------------------------- one barrier per round
@@ -1449,8 +1537,28 @@ double table_ratio()
 
 // Device bytes the rounds path allocates for k active swaps on G workgroups,
 // with `ratio` reservation slots per active swap.
+// Entries per parity of the naive variant's table of H: a power of two, at
+// least twice the active swaps.
+uint64_t naive_cap(uint64_t k)
+{
+    uint64_t c = 2;
+    while (c < 2 * k)
+        c <<= 1;
+    return c;
+}
+
+// Bytes of the array of H the flat and naive variants add for k active swaps.
+uint64_t h_table_bytes(uint64_t k, int variant)
+{
+    if (variant == RP_VARIANT_FLAT)
+        return (k * 4 + 7) / 8 * 8;
+    if (variant == RP_VARIANT_NAIVE)
+        return 2 * naive_cap(k) * 8;
+    return 0;
+}
+
 uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_out,
-                       double ratio = table_ratio())
+                       double ratio = table_ratio(), int variant = RP_VARIANT_FINAL)
 {
     const uint64_t T = std::max<uint64_t>(2, (uint64_t)std::ceil(ratio * (double)k));
     const uint64_t bmw = std::max<uint64_t>(1, (2 * k + 31) / 32);
@@ -1458,6 +1566,7 @@ uint64_t aux_bytes_for(uint64_t k, uint64_t G, uint64_t *T_out, uint64_t *bmw_ou
     if (bmw_out) *bmw_out = bmw;
     uint64_t bytes = ((T * 4 + 7) / 8) * 8     // reservation array (padded)
                    + 2 * bmw * 4               // dense window (two parities)
+                   + h_table_bytes(k, variant) // flat / naive: H of the active swaps
                    + 8;                        // error word (padded)
     if (G > 1)
         bytes += 2 * G * 8;                    // gather flags (two parities)
@@ -1587,16 +1696,17 @@ bool choose_plan1(uint64_t n, uint32_t eb, uint64_t budget, uint64_t cus, uint64
 
 // occ1: workgroups of the one-barrier kernel a compute unit holds, or 0 when
 // that path may not be used (group launches, variants).
-int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], Plan *pl);
+int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], Plan *pl,
+                 int variant = RP_VARIANT_FINAL);
 
 // occ1 > 0: the one-barrier kernel may be used; it replaces the two-barrier
 // plan unless that is the sequential loop (k = 1) or one workgroup with its
 // tables in LDS, whose rounds cost only workgroup barriers (n = 2^28 at
 // eps = 0.75: 4.7 s there against 9.0 s for four one-barrier workgroups).
 int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
-                Plan *pl, int occ1 = 0)
+                Plan *pl, int occ1 = 0, int variant = RP_VARIANT_FINAL)
 {
-    const int rc = choose_plan2(n, eb, eps, cus, occ_by_m, pl);
+    const int rc = choose_plan2(n, eb, eps, cus, occ_by_m, pl, variant);
     if (rc != RP_OK || occ1 <= 0 || pl->single || pl->lds)
         return rc;
     Plan p1 = *pl;
@@ -1606,7 +1716,8 @@ int choose_plan(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4],
 }
 
 // The two-barrier plan (rounds_body).
-int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], Plan *pl)
+int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], Plan *pl,
+                 int variant)
 {
     std::memset(pl, 0, sizeof(*pl));
     pl->bound = rp_aux_bound_words(n, eps);
@@ -1614,7 +1725,7 @@ int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], 
     pl->wpar = 2;
     const uint64_t budget = pl->bound * 8;
     // The persistent path needs k >= 2.
-    if (aux_bytes_for(2, 1, nullptr, nullptr) > budget) {
+    if (aux_bytes_for(2, 1, nullptr, nullptr, table_ratio(), variant) > budget) {
         pl->single = true;
         pl->k = 1;
         pl->G = 1;
@@ -1627,7 +1738,7 @@ int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], 
         uint64_t lo = 0, hi = (uint64_t)n;  // k never needs to exceed n
         while (lo < hi) {
             const uint64_t mid = (lo + hi + 1) / 2;
-            if (aux_bytes_for(mid, G, nullptr, nullptr, ratio) <= budget) lo = mid;
+            if (aux_bytes_for(mid, G, nullptr, nullptr, ratio, variant) <= budget) lo = mid;
             else hi = mid - 1;
         }
         return lo;
@@ -1684,7 +1795,7 @@ int choose_plan2(uint64_t n, uint32_t eb, double eps, int cus, int occ_by_m[4], 
         }
     }
     uint64_t T, bmw;
-    pl->aux_bytes = aux_bytes_for(k, G, &T, &bmw, ratio);
+    pl->aux_bytes = aux_bytes_for(k, G, &T, &bmw, ratio, variant);
     pl->k = (uint32_t)k;
     pl->G = (uint32_t)G;
     pl->M = (uint32_t)M;
@@ -1712,8 +1823,16 @@ int validate(void *A, uint64_t n, uint32_t eb, double eps)
 using KernelFn = void (*)(Params);
 
 template <int M>
-KernelFn pick_eb(int ebc)
+KernelFn pick_eb(int ebc, bool hx)
 {
+    if (hx) {
+        switch (ebc) {
+        case 4: return rp_rounds_kernel<M, 4, false, true>;
+        case 8: return rp_rounds_kernel<M, 8, false, true>;
+        case 16: return rp_rounds_kernel<M, 16, false, true>;
+        default: return rp_rounds_kernel<M, 0, false, true>;
+        }
+    }
     switch (ebc) {
     case 4: return rp_rounds_kernel<M, 4, false>;
     case 8: return rp_rounds_kernel<M, 8, false>;
@@ -1723,8 +1842,16 @@ KernelFn pick_eb(int ebc)
 }
 
 // One workgroup, one slot per lane, tables in LDS.
-KernelFn pick_lds_kernel(int ebc)
+KernelFn pick_lds_kernel(int ebc, bool hx = false)
 {
+    if (hx) {
+        switch (ebc) {
+        case 4: return rp_rounds_kernel<1, 4, true, true>;
+        case 8: return rp_rounds_kernel<1, 8, true, true>;
+        case 16: return rp_rounds_kernel<1, 16, true, true>;
+        default: return rp_rounds_kernel<1, 0, true, true>;
+        }
+    }
     switch (ebc) {
     case 4: return rp_rounds_kernel<1, 4, true>;
     case 8: return rp_rounds_kernel<1, 8, true>;
@@ -1747,13 +1874,13 @@ GroupFn pick_group_kernel(int ebc)
     }
 }
 
-KernelFn pick_kernel(int M, int ebc)
+KernelFn pick_kernel(int M, int ebc, bool hx = false)
 {
     switch (M) {
-    case 1: return pick_eb<1>(ebc);
-    case 2: return pick_eb<2>(ebc);
-    case 4: return pick_eb<4>(ebc);
-    default: return pick_eb<8>(ebc);
+    case 1: return pick_eb<1>(ebc, hx);
+    case 2: return pick_eb<2>(ebc, hx);
+    case 4: return pick_eb<4>(ebc, hx);
+    default: return pick_eb<8>(ebc, hx);
     }
 }
 
@@ -1761,6 +1888,7 @@ struct DevInfo {
     bool ok = false;
     int cus = 256;
     int occ[4][5] = {};  // [M index][eb class index] co-resident WGs per CU
+    int occx[4][5] = {}; // the same for the flat and naive variants' kernels
     int occ1[5] = {};    // one-barrier kernel, by eb1 index
 };
 
@@ -1805,6 +1933,11 @@ int device_info(int dev, DevInfo *out)
                         WG, 0) != hipSuccess)
                     return RP_EDEVICE;
                 d.occ[a][b] = std::max(occ, 1);
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &occ, reinterpret_cast<const void *>(pick_kernel(ms[a], ebs[b], true)),
+                        WG, 0) != hipSuccess)
+                    return RP_EDEVICE;
+                d.occx[a][b] = std::max(occ, 1);
             }
         const int eb1s[5] = {4, 8, 16, 64, 0};
         for (int b = 0; b < 5; b++) {
@@ -2070,6 +2203,14 @@ void setup_params(Params &p, const Plan &pl, int variant, bool lds_tab, void *A,
             p.bm = reinterpret_cast<uint32_t *>(cur);
             cur += ((uint64_t)pl.wpar * pl.bmw * 4 + 7) / 8 * 8;
         }
+        if (variant == RP_VARIANT_FLAT) {
+            p.hflat = reinterpret_cast<uint32_t *>(cur);
+            cur += h_table_bytes(pl.k, variant);
+        } else if (variant == RP_VARIANT_NAIVE) {
+            p.htab = reinterpret_cast<uint64_t *>(cur);
+            p.hcap = (uint32_t)naive_cap(pl.k);
+            cur += h_table_bytes(pl.k, variant);
+        }
         if (pl.G > 1) {
             p.flags = reinterpret_cast<uint64_t *>(cur);
             cur += 2ull * pl.G * 8;
@@ -2116,7 +2257,7 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     int rc = validate(A, n, elem_bytes, eps);
     if (rc != RP_OK)
         return rc;
-    if (variant < RP_VARIANT_FINAL || variant > RP_VARIANT_LINEAR)
+    if (variant < RP_VARIANT_FINAL || variant > RP_VARIANT_NAIVE)
         return RP_EINVAL;
     if (H != nullptr && (reinterpret_cast<uintptr_t>(H) & 7u) != 0)
         return RP_EINVAL;
@@ -2136,13 +2277,15 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
     if (rc != RP_OK)
         return rc;
     const int ebc = (elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16) ? (int)elem_bytes : 0;
+    const bool hx_plan = variant == RP_VARIANT_FLAT || variant == RP_VARIANT_NAIVE;
     int occ[4];
     for (int a = 0; a < 4; a++)
-        occ[a] = di.occ[a][eb_index(ebc)];
+        occ[a] = hx_plan ? di.occx[a][eb_index(ebc)] : di.occ[a][eb_index(ebc)];
     Plan pl;
     const int occ1 = variant == RP_VARIANT_FINAL ? di.occ1[eb1_index(eb1_of(elem_bytes))] : 0;
     rc = variant == RP_VARIANT_LINEAR ? choose_linear_plan(n, elem_bytes, eps, di.cus, occ, &pl)
-                                      : choose_plan(n, elem_bytes, eps, di.cus, occ, &pl, occ1);
+                                      : choose_plan(n, elem_bytes, eps, di.cus, occ, &pl, occ1,
+                                                    variant);
     if (rc != RP_OK)
         return rc;
 
@@ -2230,7 +2373,9 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
             return RP_EDEVICE;
         }
     } else {
-        KernelFn fn = p.lds_tab ? pick_lds_kernel(pl.eb_class) : pick_kernel((int)pl.M, pl.eb_class);
+        const bool hx = variant == RP_VARIANT_FLAT || variant == RP_VARIANT_NAIVE;
+        KernelFn fn = p.lds_tab ? pick_lds_kernel(pl.eb_class, hx)
+                                : pick_kernel((int)pl.M, pl.eb_class, hx);
         void *args[] = {&p};
         const size_t lds_bytes = p.lds_tab ? ((size_t)pl.T + 2 * (size_t)pl.bmw) * 4 : 0;
         g_ledger.lds_bytes = lds_bytes;

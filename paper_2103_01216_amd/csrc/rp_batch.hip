@@ -31,10 +31,16 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <set>
+#include <sstream>
+#include <string>
 #include <mutex>
 #include <numeric>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "rp.h"
 #include "rp_device.h"
@@ -391,6 +397,143 @@ int launch_batch(const rp_batch_request *reqs, uint32_t count,
     return RP_OK;
 }
 
+// ---------------------------------------------------- remembered schedules
+//
+// rp_batch_autotune keeps its choice in a text file, one line per tuned batch:
+//   <device key> <size mix> <wave_cutoff> <ratio16> <per_cu> <lanes> <late> <tuned_us>
+// The device key names the architecture, the compute units, the record size
+// and the batch's eps values; the size mix is the share of the sample's
+// requests in each octave of n, in thousandths ("octave:share,...").  A later
+// batch takes the line with its device key whose size mix is closest to its
+// own, if the two cumulative shares over the octaves differ by at most
+// MIX_MATCH anywhere (a Kolmogorov-Smirnov distance: batches of a few hundred
+// requests drawn from one distribution stay well within it, a mix shifted by
+// an octave in six does not).
+
+constexpr double MIX_MATCH = 0.15;
+
+std::string tune_cache_path()
+{
+    const char *v = getenv("RP_TUNE_CACHE");
+    if (v != nullptr)
+        return std::string(v);   // empty: no cache
+    const char *home = getenv("HOME");
+    if (home == nullptr || *home == '\0')
+        return std::string();
+    return std::string(home) + "/.cache/librp/batch_schedules.txt";
+}
+
+struct TuneShape {
+    std::string key;        // device, record size, eps values
+    double mix[33] = {};    // share of requests per octave of n
+};
+
+TuneShape tune_shape(int dev, const std::vector<rp_batch_request> &sample)
+{
+    TuneShape t;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    arch = arch.substr(0, arch.find(':'));
+    std::set<long> epss;
+    for (const rp_batch_request &q : sample) {
+        uint32_t b = 0;
+        while (b < 32 && (q.n >> (b + 1)) != 0)
+            b++;
+        t.mix[b] += 1.0 / (double)sample.size();
+        epss.insert(std::lround(q.eps * 1000.0));
+    }
+    std::ostringstream k;
+    k << arch << ":cu" << cus << ":eb" << sample[0].elem_bytes << ":eps";
+    for (long e : epss)
+        k << "." << e;
+    t.key = k.str();
+    return t;
+}
+
+std::string mix_text(const double *mix)
+{
+    std::ostringstream m;
+    bool first = true;
+    for (int b = 0; b < 33; b++) {
+        const long sh = std::lround(mix[b] * 1000.0);
+        if (sh > 0) {
+            m << (first ? "" : ",") << b << ":" << sh;
+            first = false;
+        }
+    }
+    return first ? std::string("0:0") : m.str();
+}
+
+bool parse_mix(const std::string &text, double *mix)
+{
+    std::istringstream in(text);
+    std::string item;
+    while (std::getline(in, item, ',')) {
+        const size_t c = item.find(':');
+        if (c == std::string::npos)
+            return false;
+        const int b = std::atoi(item.substr(0, c).c_str());
+        if (b < 0 || b > 32)
+            return false;
+        mix[b] = std::atoi(item.substr(c + 1).c_str()) / 1000.0;
+    }
+    return true;
+}
+
+bool tune_lookup(const std::string &path, const TuneShape &shape, rp_batch_schedule *out)
+{
+    if (path.empty())
+        return false;
+    std::ifstream f(path);
+    std::string line;
+    double best = MIX_MATCH + 1e-9;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string k, m;
+        rp_batch_schedule s{};
+        if (!(in >> k >> m >> s.wave_cutoff >> s.table_ratio_x16 >> s.workgroups_per_cu >>
+              s.workgroup_lanes >> s.late_loads >> s.tuned_ms_x1000) ||
+            k != shape.key || s.table_ratio_x16 == 0 || s.workgroups_per_cu == 0 ||
+            (s.workgroup_lanes != 256 && s.workgroup_lanes != 1024) || s.late_loads > 1)
+            continue;
+        double mix[33] = {};
+        if (!parse_mix(m, mix))
+            continue;
+        double ks = 0.0, ca = 0.0, cb = 0.0;
+        for (int b = 0; b < 33; b++) {
+            ca += mix[b];
+            cb += shape.mix[b];
+            ks = std::max(ks, std::fabs(ca - cb));
+        }
+        if (ks <= best) {   // the closest; among equals the later line
+            best = ks;
+            *out = s;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void tune_store(const std::string &path, const TuneShape &shape, const rp_batch_schedule &s)
+{
+    if (path.empty())
+        return;
+    // Create the directories on the way (a failure shows as a failed open).
+    for (size_t i = path.find('/', 1); i != std::string::npos; i = path.find('/', i + 1))
+        (void)mkdir(path.substr(0, i).c_str(), 0755);
+    std::ofstream f(path, std::ios::app);
+    if (f)
+        f << shape.key << ' ' << mix_text(shape.mix) << ' ' << s.wave_cutoff << ' '
+          << s.table_ratio_x16 << ' ' << s.workgroups_per_cu << ' ' << s.workgroup_lanes << ' '
+          << s.late_loads << ' ' << s.tuned_ms_x1000 << '\n';
+}
+
 void release_batch(Batch &b)
 {
     if (b.dev)
@@ -518,6 +661,20 @@ int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream
         sample.push_back(q);
     }
     const uint32_t eb = sample[0].elem_bytes;
+    // A batch of this shape on this device was tuned before: take that.
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const std::string cache = tune_cache_path();
+    const TuneShape shape = tune_shape(dev, sample);
+    rp_batch_schedule known{};
+    if (tune_lookup(cache, shape, &known)) {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_tuned = true;
+        g_tuned_sched = known;
+        if (out)
+            *out = known;
+        return RP_OK;
+    }
     void *scratch = nullptr;
     if (hipMalloc(&scratch, std::max<uint64_t>(elems * eb, 64)) != hipSuccess)
         return RP_ENOMEM;
@@ -572,6 +729,7 @@ int rp_batch_autotune(const rp_batch_request *reqs, uint32_t count, void *stream
     (void)hipEventDestroy(e1);
     (void)hipFree(scratch);
     best.tuned_ms_x1000 = (uint32_t)std::min<double>(4e9, best_ms * 1000.0);
+    tune_store(cache, shape, best);
     {
         std::lock_guard<std::mutex> lk(g_tmu);
         g_tuned = true;

@@ -1068,8 +1068,10 @@ int rp_server_create(const rp_server_config *cfg, uint64_t *server)
         std::lock_guard<std::mutex> lk(g_smu);
         s->cfg.mem_budget_bytes = g_default_budget;
     }
+    // Default large threshold: 2^22; resident mode 2^20 (a gang beats one
+    // 512-lane workgroup from there on: 2^22 in 19 ms against 52 ms).
     if (s->cfg.large_log2 == 0)
-        s->cfg.large_log2 = 22;
+        s->cfg.large_log2 = s->cfg.mode == RP_SERVE_RESIDENT ? 20 : 22;
     int cus = 0;
     if (hipGetDevice(&s->device) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) !=

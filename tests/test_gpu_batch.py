@@ -171,3 +171,34 @@ def test_large_request_in_a_batch(lanes):
         assert res[i]["status"] == 0
         assert res[i]["aux_words"] <= rp.rp_aux_bound_words(n, 0.5)
         assert np.array_equal(arrays[i].cpu().numpy(), _oracle(n, seeds[i])), (i, n)
+
+
+def test_autotune_remembers_the_schedule(tmp_path, monkeypatch):
+    """A second tuning of a batch of the same shape takes the remembered
+    schedule from the cache file instead of timing trial runs."""
+    import time
+    cache = tmp_path / "sub" / "schedules.txt"
+    monkeypatch.setenv("RP_TUNE_CACHE", str(cache))
+    sizes = workloads.batch_sizes(512, 8, 14, 5)
+    arrays = [torch.arange(int(n), dtype=torch.int32, device=DEV) for n in sizes]
+    t0 = time.perf_counter()
+    first = rp.rp_batch_autotune(arrays, seeds=list(range(len(sizes))), eps=0.5)
+    t1 = time.perf_counter()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and ":eb4:" in lines[0].split()[0]
+    # same distribution, other draws and seeds: the same line
+    sizes2 = workloads.batch_sizes(512, 8, 14, 6)
+    arrays2 = [torch.arange(int(n), dtype=torch.int32, device=DEV) for n in sizes2]
+    second = rp.rp_batch_autotune(arrays2, seeds=list(range(100, 612)), eps=0.5)
+    t2 = time.perf_counter()
+    assert second == first
+    assert t2 - t1 < 0.25 * (t1 - t0)
+    assert len(cache.read_text().splitlines()) == 1
+    # another size mix is tuned (and remembered) on its own
+    big = [torch.arange(1 << 18, dtype=torch.int32, device=DEV) for _ in range(8)]
+    rp.rp_batch_autotune(big, seeds=list(range(8)), eps=0.5)
+    assert len(cache.read_text().splitlines()) == 2
+    res = _run_batch(arrays2, list(range(100, 612)))
+    assert all(r["status"] == 0 for r in res)
+    for i in range(0, len(sizes2), 37):
+        assert np.array_equal(arrays2[i].cpu().numpy(), _oracle(int(sizes2[i]), 100 + i))

@@ -12,7 +12,7 @@ from paper_2103_01216_amd import workloads
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-VARIANTS = ["oneres", "twores", "linear"]
+VARIANTS = ["oneres", "twores", "linear", "flat", "naive"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
