@@ -494,6 +494,8 @@ def run_batch(args, log):
     torch.cuda.synchronize()
     log(f"batch: {count} instances, {total} int32 elements "
         f"(n from {sizes.min()} to {sizes.max()})")
+    # the known byte count that scales this run's rocprofv3 traffic counters
+    copy_ms = reference_copy(rp, stream, log)
 
     if args.schedule:
         v = [int(x) for x in args.schedule.split(",")]
@@ -603,7 +605,9 @@ def run_batch(args, log):
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": _traffic_bytes("batch"),
                      "kernel": "rp_batch_kernel", "kernel_ms_events": ms,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "reference_copy_bytes": COPY_BYTES,
+                     "reference_copy_gbps": 2 * COPY_BYTES / (copy_ms * 1e-3) / 1e9},
         "parity": parity,
     }
     if not args.no_cpu_baseline:
