@@ -170,6 +170,7 @@ struct Resident {
     bool stop_sent = false;
     uint32_t grid = 0;
     uint64_t posted = 0;                // entries posted so far
+    uint64_t floor = 0;                 // oldest posted entry not reaped yet (or posted)
     std::vector<uint64_t> slot_ticket;  // ticket in each ring slot (0: free)
     uint32_t busy_slots = 0;
     uint32_t wgs_out = 0;               // workgroups of the posted entries not done yet
@@ -667,11 +668,21 @@ int launch_plain_one(Server &s)
 
 // ------------------------------------------------------------ resident mode
 
+// Entries [floor, posted) hold every unfinished one: each ring slot belongs to
+// at most one of them (an entry is posted only into a free slot).  Advance
+// floor past the reaped ones.
+void res_advance_floor(Resident &R)
+{
+    while (R.floor < R.posted && R.slot_ticket[R.floor & (rpres::RING - 1)] == 0)
+        R.floor++;
+}
+
 // Fail every posted entry (the kernel or a device call failed); caller holds mu.
 void res_fail_posted(Server &s, int rc)
 {
     Resident &R = s.res;
-    for (uint32_t slot = 0; slot < rpres::RING && R.busy_slots; slot++) {
+    for (uint64_t e = R.floor; e < R.posted; e++) {
+        const uint32_t slot = (uint32_t)(e & (rpres::RING - 1));
         const uint64_t t = R.slot_ticket[slot];
         if (t == 0)
             continue;
@@ -684,6 +695,7 @@ void res_fail_posted(Server &s, int rc)
         R.busy_slots--;
         mark_done(s, t, rc);
     }
+    R.floor = R.posted;
     R.wgs_out = 0;
     s.thread_error = rc;
 }
@@ -711,7 +723,8 @@ bool res_reap(Server &s)
     if (R.busy_slots == 0)
         return progress;
     std::lock_guard<std::mutex> lk(s.mu);
-    for (uint32_t slot = 0; slot < rpres::RING && R.busy_slots; slot++) {
+    for (uint64_t e = R.floor; e < R.posted; e++) {
+        const uint32_t slot = (uint32_t)(e & (rpres::RING - 1));
         const uint64_t t = R.slot_ticket[slot];
         if (t == 0)
             continue;
@@ -736,6 +749,7 @@ bool res_reap(Server &s)
         r.rounds = R.res[slot].rounds;
         mark_done(s, t, status);
     }
+    res_advance_floor(R);
     s.stats.bytes_in_use = s.arena.in_use();
     return progress;
 }
@@ -818,9 +832,7 @@ bool res_manage(Server &s, bool stopping)
         std::lock_guard<std::mutex> lk(s.mu);
         work = R.busy_slots > 0 || !s.admitted[0].empty();
         if (R.busy_slots > 0 && !R.running)
-            for (uint32_t slot = 0; slot < rpres::RING; slot++)
-                if (R.slot_ticket[slot] != 0)
-                    first = std::min(first, s.reqs[R.slot_ticket[slot]].entry);
+            first = R.floor;   // the oldest unfinished entry
     }
     if (first != UINT64_MAX) {
         __atomic_store_n(R.stop, 0u, __ATOMIC_RELEASE);
