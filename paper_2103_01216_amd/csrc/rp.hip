@@ -704,6 +704,22 @@ constexpr double WFRAC1 = 1.5;          // window keys per active swap
 // active total then stays within a few percent of k).
 constexpr uint32_t MAX_CHUNK_LOG2 = 3;
 
+// Arrays up to this size read every active swap's records with its check
+// loads; larger ones only the winners', after the decision.  Measured on the
+// one-barrier kernel (ms, early / after): 2^20 int64 3.6 / 4.6, 2^28 int64
+// 90.8 / 95.1; but 2^26 x 64 B 66.4 / 64.7 and 2^30 int64 256.2 / 248.2 -- over
+// a few GiB of random reads the losers' extra loads miss the address
+// translation caches and cost more than the overlap saves.
+constexpr uint64_t EARLY_RECS_MAX_BYTES = 2ull << 30;
+
+uint32_t early_recs_for(uint64_t n, uint32_t eb)
+{
+    const char *v = getenv("RP_EARLY_RECS");   // tuning override: 0 or 1
+    if (v && *v)
+        return atoi(v) != 0 ? 1u : 0u;
+    return n * eb <= EARLY_RECS_MAX_BYTES ? 1u : 0u;
+}
+
 __device__ __forceinline__ uint32_t fresh_ord(uint32_t w, uint32_t j, uint32_t G, uint32_t cl)
 {
     return ((w + G * (j >> cl)) << cl) + (j & ((1u << cl) - 1u));
@@ -711,8 +727,10 @@ __device__ __forceinline__ uint32_t fresh_ord(uint32_t w, uint32_t j, uint32_t G
 
 // The rounds of one shuffle on workgroup w of its p.wg_count, with flag
 // epochs counted from `epoch0` (the last epoch used before, on the same
-// flags); returns the last epoch it used.
-template <int EB>
+// flags); returns the last epoch it used.  EARLY: every active swap reads
+// its records with its check loads (else only the winners, after the
+// decision).
+template <int EB, bool EARLY>
 __device__ __forceinline__ uint32_t rounds1_body(const Params &p, uint32_t w, uint32_t epoch0)
 {
     __shared__ uint32_t sh_scan[WAVES1];
@@ -755,6 +773,15 @@ __device__ __forceinline__ uint32_t rounds1_body(const Params &p, uint32_t w, ui
             t1 = ld(&slots[slot1(tgt, p.T)]);
             q1 = ds < W ? ld(&bm[(uint64_t)par * p.bmw + (ds >> 5)])
                         : ld(&slots[slot1(src, p.T)]);
+        }
+        // Records read early (small arrays): issued with the check loads,
+        // their latency overlaps the check's; a loser's are dropped.
+        R r_s, r_h;
+        if constexpr (EB != 0 && EARLY) {
+            if (act) {
+                r_s.load(p.A, src);
+                r_h.load(p.A, tgt);
+            }
         }
         if (rr > 0) {
             // ---- quota of this refill (the same in every workgroup): the
@@ -814,11 +841,11 @@ __device__ __forceinline__ uint32_t rounds1_body(const Params &p, uint32_t w, ui
                 retries++;
             }
         }
-        // Winners read both records now (the barrier followed every commit
-        // of the previous round, and no other winner of this round touches
-        // them); they are written back swapped after the reservations.
-        R r_s, r_h;
-        if constexpr (EB != 0) {
+        // Otherwise winners read both records now (the barrier followed every
+        // commit of the previous round, and no other winner of this round
+        // touches them).  Either way they are written back swapped after the
+        // reservations.
+        if constexpr (EB != 0 && !EARLY) {
             if (won) {
                 r_s.load(p.A, ws);
                 r_h.load(p.A, wt);
@@ -991,10 +1018,10 @@ __device__ __forceinline__ uint32_t rounds1_body(const Params &p, uint32_t w, ui
     return epoch;
 }
 
-template <int EB>
+template <int EB, bool EARLY>
 __global__ __launch_bounds__(WG1) void rp_rounds1_kernel(Params p)
 {
-    (void)rounds1_body<EB>(p, blockIdx.x - p.wg_first, 0u);
+    (void)rounds1_body<EB, EARLY>(p, blockIdx.x - p.wg_first, 0u);
 }
 
 // ------------------------------------------------------ the resident kernel
@@ -1396,11 +1423,11 @@ rp_resident_kernel(ResParams P)
         if (ok) {
             uint32_t epoch;
             switch (eb) {
-            case 4: epoch = rounds1_body<4>(p, rank, 1u); break;
-            case 8: epoch = rounds1_body<8>(p, rank, 1u); break;
-            case 16: epoch = rounds1_body<16>(p, rank, 1u); break;
-            case 64: epoch = rounds1_body<64>(p, rank, 1u); break;
-            default: epoch = rounds1_body<0>(p, rank, 1u); break;
+            case 4: epoch = rounds1_body<4, true>(p, rank, 1u); break;
+            case 8: epoch = rounds1_body<8, true>(p, rank, 1u); break;
+            case 16: epoch = rounds1_body<16, true>(p, rank, 1u); break;
+            case 64: epoch = rounds1_body<64, true>(p, rank, 1u); break;
+            default: epoch = rounds1_body<0, true>(p, rank, 1u); break;
             }
             // every member's statistics are in before the leader reads them
             ok = plain_barrier(p, rank, epoch + 1, sh_res);
@@ -1889,19 +1916,28 @@ struct DevInfo {
     int cus = 256;
     int occ[4][5] = {};  // [M index][eb class index] co-resident WGs per CU
     int occx[4][5] = {}; // the same for the flat and naive variants' kernels
-    int occ1[5] = {};    // one-barrier kernel, by eb1 index
+    int occ1[5] = {};    // one-barrier kernel (both record timings), by eb1 index
 };
 
 using KernelFn1 = void (*)(Params);
 
-KernelFn1 pick_kernel1(int eb1)
+KernelFn1 pick_kernel1(int eb1, bool early)
 {
+    if (early) {
+        switch (eb1) {
+        case 4: return rp_rounds1_kernel<4, true>;
+        case 8: return rp_rounds1_kernel<8, true>;
+        case 16: return rp_rounds1_kernel<16, true>;
+        case 64: return rp_rounds1_kernel<64, true>;
+        default: return rp_rounds1_kernel<0, true>;
+        }
+    }
     switch (eb1) {
-    case 4: return rp_rounds1_kernel<4>;
-    case 8: return rp_rounds1_kernel<8>;
-    case 16: return rp_rounds1_kernel<16>;
-    case 64: return rp_rounds1_kernel<64>;
-    default: return rp_rounds1_kernel<0>;
+    case 4: return rp_rounds1_kernel<4, false>;
+    case 8: return rp_rounds1_kernel<8, false>;
+    case 16: return rp_rounds1_kernel<16, false>;
+    case 64: return rp_rounds1_kernel<64, false>;
+    default: return rp_rounds1_kernel<0, false>;
     }
 }
 
@@ -1941,12 +1977,15 @@ int device_info(int dev, DevInfo *out)
             }
         const int eb1s[5] = {4, 8, 16, 64, 0};
         for (int b = 0; b < 5; b++) {
-            int occ = 0;
+            int occ = 0, occe = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &occ, reinterpret_cast<const void *>(pick_kernel1(eb1s[b])), WG1, 0) !=
-                hipSuccess)
+                    &occ, reinterpret_cast<const void *>(pick_kernel1(eb1s[b], false)), WG1,
+                    0) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occe, reinterpret_cast<const void *>(pick_kernel1(eb1s[b], true)), WG1,
+                    0) != hipSuccess)
                 return RP_EDEVICE;
-            d.occ1[b] = occ;
+            d.occ1[b] = std::min(occ, occe);
         }
         d.ok = true;
     }
@@ -2366,7 +2405,8 @@ int shuffle_impl(void *A, uint64_t n, uint32_t elem_bytes, const uint64_t *H, ui
         }
     } else if (pl.onebar) {
         void *args[] = {&p};
-        if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pick_kernel1(pl.eb1)),
+        const bool early = early_recs_for(n, elem_bytes) != 0;
+        if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pick_kernel1(pl.eb1, early)),
                                        dim3(pl.G), dim3(WG1), args, 0, stream) != hipSuccess) {
             (void)hipGetLastError();
             (void)release();
