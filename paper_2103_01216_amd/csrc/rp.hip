@@ -1419,15 +1419,19 @@ rp_resident_kernel(ResParams P)
             clear_rmw(&p.slots[i]);
         for (uint32_t i = rank + G * t; i < WPAR1 * bmw; i += G * RES_WG)
             clear_rmw(&p.bm[i]);
+        // The records are read after the decision: with about 220 active swaps
+        // per workgroup and one workgroup per compute unit, reading every
+        // swap's records early cost more than it saved (2^26 int64 on 64
+        // workgroups: 78.5 against 72.5 ms).
         bool ok = plain_barrier(p, rank, 1u, sh_res);
         if (ok) {
             uint32_t epoch;
             switch (eb) {
-            case 4: epoch = rounds1_body<4, true>(p, rank, 1u); break;
-            case 8: epoch = rounds1_body<8, true>(p, rank, 1u); break;
-            case 16: epoch = rounds1_body<16, true>(p, rank, 1u); break;
-            case 64: epoch = rounds1_body<64, true>(p, rank, 1u); break;
-            default: epoch = rounds1_body<0, true>(p, rank, 1u); break;
+            case 4: epoch = rounds1_body<4, false>(p, rank, 1u); break;
+            case 8: epoch = rounds1_body<8, false>(p, rank, 1u); break;
+            case 16: epoch = rounds1_body<16, false>(p, rank, 1u); break;
+            case 64: epoch = rounds1_body<64, false>(p, rank, 1u); break;
+            default: epoch = rounds1_body<0, false>(p, rank, 1u); break;
             }
             // every member's statistics are in before the leader reads them
             ok = plain_barrier(p, rank, epoch + 1, sh_res);
