@@ -494,10 +494,10 @@ int rp_list_rank(uint64_t *rec, uint64_t n, const uint64_t *prio, uint64_t seed,
  * the next free workgroup instead of with the next launch (admission at the
  * granularity of a workgroup's request boundary).  A request below
  * 2^large_log2 elements (2^20 by default) runs on one workgroup with its
- * round state in LDS;
- * a larger one on a gang of idle workgroups (up to a quarter of them, fewer
- * while other gangs are posted) that runs the one-barrier rounds with its
- * tables in the arena, counted against the admission budget and the
+ * round state in LDS; a larger one on a gang of idle workgroups (at most a
+ * quarter of them and half of those the posted requests leave free; on one
+ * workgroup when fewer than 8 would be left) that runs the one-barrier rounds
+ * with its tables in the arena, counted against the admission budget and the
  * auxiliary bound of its eps.  The kernel fills each array itself (identity,
  * or a copy from device or pinned host memory: rp_server_submit rejects any
  * other source with RP_EINVAL), leaves 20 ms after the server runs out of
