@@ -7,6 +7,8 @@ import re
 
 import numpy as np
 import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
 
 import paper_2103_01216_amd as rp
 from paper_2103_01216_amd import workloads
@@ -162,3 +164,30 @@ def test_set_mem_budget_host_only():
     L.rp_set_mem_budget.argtypes = [ctypes.c_uint64]
     assert L.rp_set_mem_budget(0) == rp.RP_EINVAL
     assert L.rp_set_mem_budget(64 << 30) == rp.RP_OK
+
+
+_sizes = st.one_of(
+    st.integers(min_value=2, max_value=(1 << 32) - 1),
+    st.builds(lambda e, d: max(2, min((1 << 32) - 1, (1 << e) + d)),
+              st.integers(min_value=1, max_value=31), st.integers(min_value=-3, max_value=3)))
+
+
+@settings(max_examples=400, deadline=None, derandomize=True)
+@given(n=_sizes, eps=st.floats(min_value=0.01, max_value=0.99),
+       eb=st.sampled_from([4, 8, 12, 16, 20, 64, 128, 252, 256]))
+def test_plan_properties_over_the_argument_space(n, eps, eb):
+    """Every plan (host only; an MI355X assumed) keeps its auxiliary words
+    within floor(n^(1-eps)), has at least one active swap and no more than n,
+    and counts at least one in-flight word per active swap."""
+    p = rp.rp_plan(n, eb, eps)
+    assert p["status"] == 0
+    assert p["aux_bound_words"] == rp.rp_aux_bound_words(n, eps)
+    assert p["aux_words"] <= p["aux_bound_words"]
+    assert 1 <= p["k"] <= n
+    assert p["k"] <= p["grid"] * 256 * p["slots_per_lane"]
+    assert p["inflight_words"] >= p["k"]
+    if p["k"] > 1:
+        assert p["table_slots"] >= 1
+    # a larger eps never allows more auxiliary words
+    if eps + 0.05 < 1.0:
+        assert rp.rp_aux_bound_words(n, eps + 0.05) <= p["aux_bound_words"]
